@@ -1,0 +1,169 @@
+/*
+ * h2dlp -- H2-compressed boundary double-layer operator of the Fredkin-Koehler
+ * FEM/BEM magnetostatic method, on AMD Instinct MI355X (gfx950).
+ *
+ * The operator (Hertel, Christophersen & Boerm, arXiv:1811.05731, Section 3,
+ * eqs. matrix_definition and denseMat) maps the boundary trace u1 of the
+ * Neumann potential to the Dirichlet data u2 of the harmonic part,
+ *
+ *     u2 = M u1 = (K + D) u1,
+ *     K_ij = (1/4pi) int phi_j(y) n(y).(xi_i - y)/|xi_i - y|^3 dS_y,
+ *     D_ii = Psi(xi_i)/(4 pi) - 1,
+ *
+ * with collocation at the mesh nodes xi_i, P1 hat functions phi_j and the
+ * interior solid angle Psi.  K is held as an H2 matrix (Section 4): tensor
+ * Chebyshev interpolation of order m on a bounding-box cluster tree with
+ * eta-admissibility; inadmissible leaf blocks hold exact entries.
+ *
+ * Conventions shared by every call:
+ *  - No call throws; every failure returns a negative code and leaves a
+ *    message for h2dlp_last_error() (thread-local).
+ *  - Host pointers are read during the call only; the caller keeps ownership.
+ *  - Device pointers (u1, u2, workspace) are HIP device memory on the handle's
+ *    device, owned by the caller.
+ */
+#ifndef H2DLP_H
+#define H2DLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define H2DLP_OK       0
+#define H2DLP_EINVAL  -1   /* bad argument, bad mesh (see h2dlp_last_error) */
+#define H2DLP_ENOMEM  -2   /* device allocation failed or workspace too small */
+#define H2DLP_EDEVICE -3   /* a HIP runtime call failed */
+#define H2DLP_ENOTSUP -4   /* precision / device / size not supported */
+
+/* arithmetic of the compressed operator (coupling, bases, transfers, near blocks) */
+#define H2DLP_FP64    0    /* everything in FP64 */
+#define H2DLP_FP32    1    /* FP32 storage and accumulation; FP64 diagonal and near-singular entries */
+#define H2DLP_BF16X3  2    /* as FP32, coupling products as split bf16 x3 on MFMA, FP32 accumulation */
+
+/* element type of u1 / u2 */
+#define H2DLP_IO_F64  0
+#define H2DLP_IO_F32  1
+
+/* Closed, consistently oriented triangle surface (Section 3: nodes xi_i and the
+ * P1 basis on the boundary of the magnetic body).  xyz: n_nodes x 3 row-major
+ * FP64; tri: n_tris x 3 row-major, 0-based node indices, counter-clockwise seen
+ * from outside (outward normals).  Both host memory. */
+typedef struct {
+    int64_t        n_nodes;
+    const double*  xyz;
+    int64_t        n_tris;
+    const int32_t* tri;
+} h2dlp_mesh;
+
+/* Build parameters.  order m in [1, 8] (k = m^3 interpolation points per
+ * cluster); leaf in [1, 64] (maximum leaf cluster size); eta > 0
+ * (admissibility max(diam_t, diam_s) <= eta dist(t, s)); alpha in [0, 1]
+ * (each cluster box side is widened to at least alpha times its longest side);
+ * device: HIP ordinal or -1 for the current device; stream: hipStream_t for the
+ * build kernels, NULL for the null stream. */
+typedef struct {
+    int    order;
+    int    leaf;
+    double eta;
+    int    precision;
+    double alpha;
+    int    device;
+    void*  stream;
+} h2dlp_options;
+
+typedef struct h2dlp_ctx* h2dlp_handle;
+
+/* Sizes of a built operator. */
+typedef struct {
+    int64_t n_nodes, n_tris;
+    int32_t order, leaf, k, precision;
+    int32_t depth;              /* deepest cluster level (root = 0) */
+    int64_t n_clusters, n_leaves;
+    int64_t n_far, n_near;      /* admissible blocks, inadmissible leaf blocks */
+    int64_t coupling_entries;   /* n_far * k * k */
+    int64_t near_entries;       /* sum over near blocks of |t| |s| */
+    int64_t nearsing_entries;   /* near-singular entries kept in FP64 (FP32/BF16X3 only) */
+    int64_t bytes_coupling, bytes_near, bytes_bases, bytes_transfer, bytes_other;
+    int64_t bytes_resident;     /* all device memory held by the handle */
+    int64_t workspace_bytes;    /* per concurrent apply (one 16-column pass) */
+    double  compression;        /* 1 - (H2 bytes)/(8 N^2), the paper's ratio r (Section 6.1) */
+} h2dlp_stats;
+
+/* Fill *opt with defaults: order 4, leaf 32, eta 2, FP64, alpha 0.1, device -1, stream NULL. */
+void h2dlp_default_options(h2dlp_options* opt);
+
+/* Build the H2 operator for `mesh` (copied; the caller may free it on return).
+ * The handle owns its device memory until h2dlp_free.  Returns NULL on error. */
+h2dlp_handle h2dlp_build(const h2dlp_mesh* mesh, int order, int leaf, double eta);
+
+/* As h2dlp_build with full options; *out receives the handle.  Errors:
+ * EINVAL (NULL pointers, order/leaf/eta/alpha out of range, index out of range,
+ * repeated vertex or zero-area triangle, open or non-manifold edge, inconsistent
+ * orientation, non-positive enclosed volume, coincident nodes), ENOMEM, EDEVICE,
+ * ENOTSUP (no gfx950 device). */
+int h2dlp_build_ex(const h2dlp_mesh* mesh, const h2dlp_options* opt, h2dlp_handle* out);
+
+/* Host-only planning: the block structure and every byte count of h2dlp_stats
+ * for `mesh` and `opt`, without touching a GPU (no HIP call).  The handle
+ * supports h2dlp_info, h2dlp_bytes, h2dlp_export_structure and h2dlp_free;
+ * apply on it returns EINVAL.  Meant for admission by HBM budget before a
+ * build, and for checking the structure.  Errors as h2dlp_build_ex, without
+ * EDEVICE/ENOTSUP for the device. */
+int h2dlp_plan(const h2dlp_mesh* mesh, const h2dlp_options* opt, h2dlp_handle* out);
+
+/* u2 = M u1 for nrhs right-hand sides (eq. denseMat).  u1, u2: device, FP64,
+ * (nrhs, n_nodes) row-major, one contiguous vector per right-hand side, in the
+ * caller's node order; must not overlap.  Asynchronous on the null stream, using
+ * the handle's own workspace (not safe to call concurrently on one handle).
+ * Errors: EINVAL (NULL, nrhs < 1), EDEVICE. */
+int h2dlp_apply(h2dlp_handle h, const double* u1, double* u2, int nrhs);
+
+/* As h2dlp_apply, with io_dtype (H2DLP_IO_F64 / H2DLP_IO_F32), a hipStream_t
+ * (NULL = null stream) and a caller-owned device workspace of at least
+ * h2dlp_stats.workspace_bytes (NULL = the handle's own).  Distinct workspaces
+ * make concurrent applies of one handle on different streams safe.  Right-hand
+ * sides are processed 16 at a time.  Errors: EINVAL, ENOMEM (workspace_bytes
+ * too small), EDEVICE. */
+int h2dlp_apply_ex(h2dlp_handle h, const void* u1, void* u2, int nrhs, int io_dtype,
+                   void* stream, void* workspace, size_t workspace_bytes);
+
+/* Device bytes held by the handle and needed per concurrent apply (admission by HBM budget). */
+int h2dlp_bytes(h2dlp_handle h, size_t* resident, size_t* workspace);
+
+int h2dlp_info(h2dlp_handle h, h2dlp_stats* st);
+
+/* Copy out the block structure (host arrays, sizes from h2dlp_info), in the
+ * preorder numbering of the cluster tree (root 0, first child's subtree first):
+ *   perm[n_nodes]          node index of each position in cluster order
+ *   clusters[n_clusters*6] begin, end, level, parent, child0, child1 (-1 = none)
+ *   boxes[n_clusters*6]    lo_x, lo_y, lo_z, hi_x, hi_y, hi_z of the inflated box
+ *   far[n_far*2], near[n_near*2]  (target, source) cluster pairs, sorted
+ * Any pointer may be NULL to skip that array. */
+int h2dlp_export_structure(h2dlp_handle h, int64_t* perm, int64_t* clusters, double* boxes,
+                           int64_t* far, int64_t* near);
+
+/* The diagonal D_ii = Psi_i/(4 pi) - 1 as computed on the device (host array, node order). */
+int h2dlp_export_diagonal(h2dlp_handle h, double* diag);
+
+void h2dlp_free(h2dlp_handle h);
+
+const char* h2dlp_last_error(void);
+
+/* Kernel timing with hipEvents recorded around every launch of the apply, on
+ * the stream the launch goes to.  Kinds: 0 permute, 1 leaf forward, 2 upward
+ * transfer, 3 coupling, 4 downward transfer, 5 leaf backward + near field +
+ * diagonal.  h2dlp_profile_read synchronises the recorded events and returns
+ * the summed milliseconds and launch counts per kind (n_kinds <= 6). */
+#define H2DLP_NKINDS 6
+int h2dlp_profile(h2dlp_handle h, int enable);
+int h2dlp_profile_read(h2dlp_handle h, double* ms, int64_t* launches, int n_kinds, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* H2DLP_H */

@@ -1,0 +1,680 @@
+// C ABI of the library (include/h2dlp.h): build, apply, sizes, export, errors.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/h2dlp.h"
+#include "kernels.h"
+#include "structure.h"
+
+using namespace h2dlp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+struct HipError {
+    hipError_t err;
+    std::string where;
+};
+
+void check(hipError_t e, const char* where) {
+    if (e != hipSuccess) throw HipError{e, where};
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Gauss-Legendre nodes/weights on [-1, 1] by Newton's method on the
+// three-term recurrence of the Legendre polynomials.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        double z = std::cos(pi * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = z;
+            for (int j = 2; j <= n; ++j) {
+                const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            const double dz = p1 / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-16) break;
+        }
+        double p0 = 1.0, p1 = z;
+        for (int j = 2; j <= n; ++j) {
+            const double p2 = ((2.0 * j - 1.0) * z * p1 - (j - 1.0) * p0) / j;
+            p0 = p1;
+            p1 = p2;
+        }
+        if (n == 1) { p1 = z; p0 = 1.0; }
+        dp = n * (z * p1 - p0) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+// Collapsed-square rule on the reference triangle {u, v >= 0, u + v <= 1},
+// exact for total degree `degree`: v = (1 - u) t, Jacobian (1 - u).
+std::vector<double> triangle_rule(int degree) {
+    const int n = (degree + 3) / 2;
+    std::vector<double> x, w;
+    gauss_legendre(n, x, w);
+    std::vector<double> out;
+    for (int a = 0; a < n; ++a)
+        for (int b = 0; b < n; ++b) {
+            const double u = 0.5 * (x[a] + 1.0), t = 0.5 * (x[b] + 1.0);
+            out.push_back(u);
+            out.push_back((1.0 - u) * t);
+            out.push_back(0.25 * w[a] * w[b] * (1.0 - u));
+        }
+    return out;
+}
+
+}  // namespace
+
+struct h2dlp_ctx {
+    h2dlp_options opt{};
+    int device = -1;                 // -1 until device memory exists
+    int m = 0, k = 0, prec = 0;
+    size_t elem = 8;                 // bytes per stored value of the operator
+    Structure S;
+    int32_t n_clusters = 0, n_leaves = 0;
+    std::vector<int32_t> gid_of_pre;
+    std::vector<int32_t> level_off;  // clusters of level l: gids [level_off[l], level_off[l+1])
+    // device
+    std::vector<DevBuf> bufs;
+    int32_t* d_perm = nullptr;
+    double* d_diag = nullptr;
+    int32_t* d_child0 = nullptr;
+    int32_t* d_child1 = nullptr;
+    int32_t* d_parent = nullptr;
+    void* d_e = nullptr;
+    void* d_pool_wt = nullptr;
+    void* d_pool_s = nullptr;
+    void* d_pool_leaf = nullptr;
+    ItemDesc* d_items_fwd = nullptr;
+    BlkDesc* d_blks_fwd = nullptr;
+    ItemDesc* d_items_cpl = nullptr;
+    BlkDesc* d_blks_cpl = nullptr;
+    ItemDesc* d_items_leaf = nullptr;
+    BlkDesc* d_blks_leaf = nullptr;
+    int64_t* d_ns_off = nullptr;
+    int32_t* d_ns_col = nullptr;
+    double* d_ns_val = nullptr;
+    void* d_ws = nullptr;
+    size_t ws_bytes = 0, ws_x = 0, ws_xh = 0;
+    int32_t n_items_fwd = 0, n_items_cpl = 0, n_items_leaf = 0;
+    int32_t rt_leaf = 1;
+    bool materialized = false;
+    // host-side plan
+    std::vector<int32_t> child0, child1, parent;
+    std::vector<double> boxes;
+    std::vector<LeafDesc> leaves, vleaves;
+    std::vector<FarDesc> fars;
+    std::vector<NearDesc> nears;
+    std::vector<ItemDesc> items_fwd, items_cpl, items_leaf;
+    std::vector<BlkDesc> blks_fwd, blks_cpl, blks_leaf;
+    int64_t off_wt = 0, off_s = 0, off_l = 0;
+    h2dlp_stats st{};
+    // profiling
+    bool prof = false;
+    struct Rec { int kind; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    double prof_ms[H2DLP_NKINDS] = {0};
+    int64_t prof_n[H2DLP_NKINDS] = {0};
+
+    ~h2dlp_ctx() {
+        if (device < 0) return;   // plan only: nothing on a device
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(device);
+        for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+        (void)hipSetDevice(cur);
+    }
+
+    template <typename P>
+    P* alloc(size_t bytes, int64_t* account) {
+        DevBuf b;
+        b.bytes = bytes;
+        if (bytes > 0) {
+            const hipError_t e = hipMalloc(&b.p, bytes);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                throw std::bad_alloc();
+            }
+        }
+        bufs.push_back(b);
+        if (account) *account += int64_t(bytes);
+        return static_cast<P*>(b.p);
+    }
+
+    template <typename V>
+    typename V::value_type* upload(const V& v, int64_t* account, hipStream_t s) {
+        typedef typename V::value_type E;
+        E* p = alloc<E>(v.size() * sizeof(E), account);
+        if (!v.empty()) check(hipMemcpyAsync(p, v.data(), v.size() * sizeof(E), hipMemcpyHostToDevice, s), "upload");
+        return p;
+    }
+
+    void release(void* p) {
+        for (auto& b : bufs)
+            if (b.p == p) {
+                hipFree(b.p);
+                b.p = nullptr;
+                b.bytes = 0;
+            }
+    }
+};
+
+namespace {
+
+// Host part of a build: block structure, level-order numbering, pool layouts
+// and block descriptors, byte counts.  No HIP call.
+int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
+    h->opt = *o;
+    h->m = o->order;
+    h->k = o->order * o->order * o->order;
+    h->prec = o->precision;
+    h->elem = h->prec == H2DLP_FP64 ? 8 : 4;
+    const bool fp64 = h->prec == H2DLP_FP64;
+
+    std::string err = build_structure(h->S, mesh->xyz, mesh->n_nodes, mesh->tri, mesh->n_tris, o->leaf, o->eta,
+                                      o->alpha, !fp64);
+    if (!err.empty()) return fail(H2DLP_EINVAL, err);
+    Structure& S = h->S;
+    const int64_t N = S.n_nodes, T = S.n_tris;
+    const int m = h->m, k = h->k;
+    const int32_t C = int32_t(S.cl.size());
+    h->n_clusters = C;
+
+    // level-major cluster numbering (clusters of one level contiguous, left to right)
+    std::vector<int32_t> order(C);
+    for (int32_t c = 0; c < C; ++c) order[c] = c;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return S.cl[a].level < S.cl[b].level; });
+    h->gid_of_pre.assign(C, 0);
+    for (int32_t g = 0; g < C; ++g) h->gid_of_pre[order[g]] = g;
+    h->level_off.assign(S.depth + 2, 0);
+    for (int32_t c = 0; c < C; ++c) h->level_off[S.cl[c].level + 1]++;
+    for (int l = 0; l <= S.depth; ++l) h->level_off[l + 1] += h->level_off[l];
+    h->child0.assign(C, -1);
+    h->child1.assign(C, -1);
+    h->parent.assign(C, -1);
+    h->boxes.assign(6 * size_t(C), 0.0);
+    for (int32_t c = 0; c < C; ++c) {
+        const int32_t g = h->gid_of_pre[c];
+        const Cluster& X = S.cl[c];
+        if (!X.leaf()) { h->child0[g] = h->gid_of_pre[X.child0]; h->child1[g] = h->gid_of_pre[X.child1]; }
+        if (X.parent >= 0) h->parent[g] = h->gid_of_pre[X.parent];
+        for (int a = 0; a < 3; ++a) { h->boxes[6 * size_t(g) + a] = X.lo[a]; h->boxes[6 * size_t(g) + 3 + a] = X.hi[a]; }
+    }
+    std::vector<int32_t> leaf_pre;
+    for (int32_t g = 0; g < C; ++g)
+        if (S.cl[order[g]].leaf()) leaf_pre.push_back(order[g]);
+    h->n_leaves = int32_t(leaf_pre.size());
+
+    // leaf forward: one item and one block (W_s^T, k x n_s) per leaf
+    h->leaves.resize(leaf_pre.size());
+    int64_t off_wt = 0;
+    for (size_t q = 0; q < leaf_pre.size(); ++q) {
+        const Cluster& X = S.cl[leaf_pre[q]];
+        const int32_t g = h->gid_of_pre[leaf_pre[q]];
+        h->leaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), g, 0, off_wt};
+        h->items_fwd.push_back(ItemDesc{g * k, k, int32_t(h->blks_fwd.size()), int32_t(h->blks_fwd.size() + 1)});
+        h->blks_fwd.push_back(BlkDesc{off_wt, int32_t(X.size()), int32_t(X.begin)});
+        off_wt += int64_t(k) * X.size();
+    }
+    // coupling: one item per cluster (level order), its blocks sorted by source
+    std::vector<std::vector<int32_t>> far_by_t(C);
+    for (size_t b = 0; b < S.far.size(); ++b)
+        far_by_t[h->gid_of_pre[S.far[b].first]].push_back(h->gid_of_pre[S.far[b].second]);
+    int64_t off_s = 0;
+    for (int32_t g = 0; g < C; ++g) {
+        auto& lst = far_by_t[g];
+        std::sort(lst.begin(), lst.end());
+        h->items_cpl.push_back(ItemDesc{g * k, k, int32_t(h->blks_cpl.size()), int32_t(h->blks_cpl.size() + lst.size())});
+        for (int32_t s : lst) {
+            h->fars.push_back(FarDesc{g, s, off_s});
+            h->blks_cpl.push_back(BlkDesc{off_s, k, s * k});
+            off_s += int64_t(k) * k;
+        }
+    }
+    // leaf output: V_t (n_t x k) then the near blocks of t (sorted by source position)
+    std::vector<std::vector<int32_t>> near_by_t(C);
+    for (size_t b = 0; b < S.near.size(); ++b) near_by_t[S.near[b].first].push_back(S.near[b].second);
+    h->vleaves.resize(leaf_pre.size());
+    int64_t off_l = 0, near_entries = 0;
+    for (size_t q = 0; q < leaf_pre.size(); ++q) {
+        const int32_t t = leaf_pre[q];
+        const Cluster& X = S.cl[t];
+        auto& lst = near_by_t[t];
+        std::sort(lst.begin(), lst.end(), [&](int32_t a, int32_t b) { return S.cl[a].begin < S.cl[b].begin; });
+        h->items_leaf.push_back(ItemDesc{int32_t(X.begin), int32_t(X.size()), int32_t(h->blks_leaf.size()),
+                                         int32_t(h->blks_leaf.size() + 1 + lst.size())});
+        h->vleaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), h->gid_of_pre[t], 0, off_l};
+        h->blks_leaf.push_back(BlkDesc{off_l, k, SRC1 | (h->gid_of_pre[t] * k)});
+        off_l += int64_t(X.size()) * k;
+        for (int32_t s : lst) {
+            const Cluster& Y = S.cl[s];
+            h->nears.push_back(NearDesc{int32_t(X.begin), int32_t(X.size()), int32_t(Y.begin), int32_t(Y.size()), off_l});
+            h->blks_leaf.push_back(BlkDesc{off_l, int32_t(Y.size()), int32_t(Y.begin)});
+            off_l += int64_t(X.size()) * Y.size();
+            near_entries += int64_t(X.size()) * Y.size();
+        }
+    }
+    h->n_items_fwd = int32_t(h->items_fwd.size());
+    h->n_items_cpl = int32_t(h->items_cpl.size());
+    h->n_items_leaf = int32_t(h->items_leaf.size());
+    h->rt_leaf = (o->leaf + 15) / 16;
+    h->off_wt = off_wt;
+    h->off_s = off_s;
+    h->off_l = off_l;
+
+    const size_t e = h->elem;
+    h->ws_x = align_up(e * size_t(N) * RHS_TILE);
+    h->ws_xh = align_up(e * size_t(C) * k * RHS_TILE);
+    h->ws_bytes = h->ws_x + 2 * h->ws_xh;
+
+    h2dlp_stats& st = h->st;
+    st = h2dlp_stats{};
+    st.n_nodes = N;
+    st.n_tris = T;
+    st.order = m;
+    st.leaf = o->leaf;
+    st.k = k;
+    st.precision = h->prec;
+    st.depth = S.depth;
+    st.n_clusters = C;
+    st.n_leaves = h->n_leaves;
+    st.n_far = int64_t(S.far.size());
+    st.n_near = int64_t(S.near.size());
+    st.coupling_entries = off_s;
+    st.near_entries = near_entries;
+    st.nearsing_entries = fp64 ? 0 : int64_t(S.ring_pos.size());
+    st.bytes_coupling = int64_t(e * size_t(off_s));
+    st.bytes_near = int64_t(e * size_t(near_entries));
+    if (!fp64) st.bytes_near += int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8));
+    st.bytes_bases = int64_t(e * size_t(off_wt + N * int64_t(k)));
+    st.bytes_transfer = int64_t(e * size_t(C) * 3 * m * m);
+    st.bytes_other = int64_t(N * 4 + 3 * int64_t(C) * 4 + N * 8 +
+                             (h->items_fwd.size() + h->items_cpl.size() + h->items_leaf.size()) * sizeof(ItemDesc) +
+                             (h->blks_fwd.size() + h->blks_cpl.size() + h->blks_leaf.size()) * sizeof(BlkDesc));
+    st.workspace_bytes = int64_t(h->ws_bytes);
+    st.bytes_resident = st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer + st.bytes_other +
+                        st.workspace_bytes;
+    const double h2_bytes = double(st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer);
+    st.compression = 1.0 - h2_bytes / (8.0 * double(N) * double(N));
+    return H2DLP_OK;
+}
+
+// Device part of a build: upload, generate every block in FP64 arithmetic, free the build-only arrays.
+int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
+    Structure& S = h->S;
+    const int64_t N = S.n_nodes, T = S.n_tris;
+    const int m = h->m;
+    const int32_t C = h->n_clusters;
+    const bool fp64 = h->prec == H2DLP_FP64;
+    const size_t e = h->elem;
+    int64_t kept = 0, scratch = 0;
+    std::vector<int32_t> perm32(S.perm.begin(), S.perm.end());
+    h->d_perm = h->upload(perm32, &kept, stream);
+    h->d_child0 = h->upload(h->child0, &kept, stream);
+    h->d_child1 = h->upload(h->child1, &kept, stream);
+    h->d_parent = h->upload(h->parent, &kept, stream);
+    h->d_diag = h->alloc<double>(sizeof(double) * N, &kept);
+    h->d_e = h->alloc<void>(e * size_t(C) * 3 * m * m, &kept);
+    h->d_pool_wt = h->alloc<void>(e * size_t(h->off_wt), &kept);
+    h->d_pool_s = h->alloc<void>(e * size_t(h->off_s), &kept);
+    h->d_pool_leaf = h->alloc<void>(e * size_t(h->off_l), &kept);
+    h->d_items_fwd = h->upload(h->items_fwd, &kept, stream);
+    h->d_blks_fwd = h->upload(h->blks_fwd, &kept, stream);
+    h->d_items_cpl = h->upload(h->items_cpl, &kept, stream);
+    h->d_blks_cpl = h->upload(h->blks_cpl, &kept, stream);
+    h->d_items_leaf = h->upload(h->items_leaf, &kept, stream);
+    h->d_blks_leaf = h->upload(h->blks_leaf, &kept, stream);
+    if (!fp64) {
+        h->d_ns_off = h->upload(S.ring_off, &kept, stream);
+        std::vector<int32_t> col(S.ring_pos.size());
+        for (size_t q = 0; q < col.size(); ++q) col[q] = S.perm[S.ring_pos[q]];
+        h->d_ns_col = h->upload(col, &kept, stream);
+        const size_t nb = sizeof(double) * std::max<size_t>(1, col.size());
+        h->d_ns_val = h->alloc<double>(nb, &kept);
+        check(hipMemsetAsync(h->d_ns_val, 0, nb, stream), "clear near-singular values");
+    }
+    std::vector<double> quad = triangle_rule(3 * (m - 1));
+    std::vector<void*> temp;
+    auto tmp = [&](auto* p) { temp.push_back(static_cast<void*>(p)); return p; };
+    double* d_xyz = tmp(h->upload(S.xyz, &scratch, stream));
+    int32_t* d_tri = tmp(h->upload(S.tri, &scratch, stream));
+    int64_t* d_inc_off = tmp(h->upload(S.inc_off, &scratch, stream));
+    int32_t* d_inc_tri = tmp(h->upload(S.inc_tri, &scratch, stream));
+    int32_t* d_inc_loc = tmp(h->upload(S.inc_loc, &scratch, stream));
+    double* d_tgeo = tmp(h->alloc<double>(sizeof(double) * 4 * T, &scratch));
+    double* d_boxes = tmp(h->upload(h->boxes, &scratch, stream));
+    double* d_quad = tmp(h->upload(quad, &scratch, stream));
+    LeafDesc* d_leaves = tmp(h->upload(h->leaves, &scratch, stream));
+    LeafDesc* d_vleaves = tmp(h->upload(h->vleaves, &scratch, stream));
+    FarDesc* d_far = tmp(h->upload(h->fars, &scratch, stream));
+    NearDesc* d_near = tmp(h->upload(h->nears, &scratch, stream));
+    int32_t* d_ring_pos = fp64 ? nullptr : tmp(h->upload(S.ring_pos, &scratch, stream));
+
+    DevMesh dm{d_xyz, d_tri, d_inc_off, d_inc_tri, d_inc_loc, d_tgeo, h->d_perm};
+    check(launch_tri_geometry(d_xyz, d_tri, T, d_tgeo, stream), "triangle geometry");
+    check(launch_diagonal(dm, N, h->d_diag, stream), "diagonal");
+    check(launch_build_wt(dm, d_boxes, m, d_quad, int(quad.size() / 3), d_leaves, int64_t(h->leaves.size()), h->prec,
+                          h->d_pool_wt, stream), "column basis");
+    check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf, stream),
+          "row basis");
+    check(launch_build_transfer(d_boxes, h->d_parent, C, m, h->prec, h->d_e, stream), "transfer");
+    check(launch_build_coupling(d_boxes, m, d_far, int64_t(h->fars.size()), h->prec, h->d_pool_s, stream), "coupling");
+    check(launch_build_near(dm, d_near, int64_t(h->nears.size()), h->prec, h->d_pool_leaf,
+                            fp64 ? nullptr : h->d_ns_off, d_ring_pos, fp64 ? nullptr : h->d_ns_val, stream),
+          "near field");
+    check(hipStreamSynchronize(stream), "build synchronize");
+    for (void* p : temp) h->release(p);
+    h->d_ws = h->alloc<void>(h->ws_bytes, &kept);
+    // host-side descriptors are no longer needed
+    h->leaves.clear(); h->leaves.shrink_to_fit();
+    h->vleaves.clear(); h->vleaves.shrink_to_fit();
+    h->fars.clear(); h->fars.shrink_to_fit();
+    h->nears.clear(); h->nears.shrink_to_fit();
+    h->materialized = true;
+    return H2DLP_OK;
+}
+
+h2dlp_ctx* as_ctx(h2dlp_handle h) { return reinterpret_cast<h2dlp_ctx*>(h); }
+
+void rec_begin(h2dlp_ctx* h, hipStream_t s, hipEvent_t* a) {
+    if (!h->prof) return;
+    check(hipEventCreate(a), "event");
+    check(hipEventRecord(*a, s), "event record");
+}
+void rec_end(h2dlp_ctx* h, hipStream_t s, int kind, hipEvent_t a) {
+    if (!h->prof) return;
+    hipEvent_t b;
+    check(hipEventCreate(&b), "event");
+    check(hipEventRecord(b, s), "event record");
+    h->recs.push_back({kind, a, b});
+}
+
+int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStream_t s, void* ws) {
+    const int64_t N = h->S.n_nodes;
+    const int m = h->m, k = h->k, prec = h->prec;
+    char* base = static_cast<char*>(ws);
+    void* x = base;
+    void* xh = base + h->ws_x;
+    void* yh = base + h->ws_x + h->ws_xh;
+    const size_t io_elem = io == H2DLP_IO_F32 ? 4 : 8;
+    for (int c0 = 0; c0 < nrhs; c0 += RHS_TILE) {
+        const int nr = std::min(RHS_TILE, nrhs - c0);
+        const void* u1p = static_cast<const char*>(u1) + io_elem * size_t(c0) * N;
+        void* u2p = static_cast<char*>(u2) + io_elem * size_t(c0) * N;
+        hipEvent_t ev = nullptr;
+        rec_begin(h, s, &ev);
+        check(launch_permute(u1p, io, N, nr, h->d_perm, x, prec, s), "permute");
+        rec_end(h, s, 0, ev);
+
+        ProductArgs fwd{h->d_items_fwd, h->n_items_fwd, (k + 15) / 16, h->d_blks_fwd, h->d_pool_wt, x, nullptr, xh};
+        rec_begin(h, s, &ev);
+        check(launch_product_store(fwd, prec, true, s), "leaf forward");
+        rec_end(h, s, 1, ev);
+
+        for (int l = h->S.depth - 1; l >= 0; --l) {
+            rec_begin(h, s, &ev);
+            check(launch_upward(h->level_off[l], h->level_off[l + 1], h->d_child0, h->d_child1, h->d_e, xh, m, prec, s),
+                  "upward");
+            rec_end(h, s, 2, ev);
+        }
+
+        ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
+        rec_begin(h, s, &ev);
+        check(launch_product_store(cpl, prec, false, s), "coupling");
+        rec_end(h, s, 3, ev);
+
+        for (int l = 1; l <= h->S.depth; ++l) {
+            rec_begin(h, s, &ev);
+            check(launch_downward(h->level_off[l], h->level_off[l + 1], h->d_parent, h->d_e, yh, m, prec, s), "downward");
+            rec_end(h, s, 4, ev);
+        }
+
+        ProductArgs leaf{h->d_items_leaf, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
+        LeafEpilogue epi{h->d_perm, h->d_diag, u1p, u2p, N, nr, io, h->d_ns_off, h->d_ns_col, h->d_ns_val};
+        rec_begin(h, s, &ev);
+        check(launch_product_leaf(leaf, epi, prec, s), "leaf output");
+        rec_end(h, s, 5, ev);
+    }
+    return H2DLP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void h2dlp_default_options(h2dlp_options* o) {
+    if (!o) return;
+    o->order = 4;
+    o->leaf = 32;
+    o->eta = 2.0;
+    o->precision = H2DLP_FP64;
+    o->alpha = 0.1;
+    o->device = -1;
+    o->stream = nullptr;
+}
+
+static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle* out) {
+    if (!out) return fail(H2DLP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mesh || !o) return fail(H2DLP_EINVAL, "mesh or options is NULL");
+    if (!mesh->xyz || !mesh->tri) return fail(H2DLP_EINVAL, "mesh arrays are NULL");
+    if (mesh->n_nodes < 4 || mesh->n_tris < 4) return fail(H2DLP_EINVAL, "mesh needs at least 4 nodes and 4 triangles");
+    if (mesh->n_nodes > (int64_t(1) << 30) || mesh->n_tris > (int64_t(1) << 30))
+        return fail(H2DLP_ENOTSUP, "mesh larger than 2^30 nodes or triangles");
+    if (o->order < 1 || o->order > 8) return fail(H2DLP_EINVAL, "order must be in [1, 8]");
+    if (o->leaf < 1 || o->leaf > 64) return fail(H2DLP_EINVAL, "leaf must be in [1, 64]");
+    if (!(o->eta > 0.0) || !std::isfinite(o->eta)) return fail(H2DLP_EINVAL, "eta must be positive");
+    if (!(o->alpha >= 0.0 && o->alpha <= 1.0)) return fail(H2DLP_EINVAL, "alpha must be in [0, 1]");
+    if (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32 && o->precision != H2DLP_BF16X3)
+        return fail(H2DLP_EINVAL, "unknown precision");
+    if (o->precision == H2DLP_BF16X3) return fail(H2DLP_ENOTSUP, "BF16X3 not available in this build");
+    return H2DLP_OK;
+}
+
+int h2dlp_plan(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle* out) {
+    int rc = check_args(mesh, o, out);
+    if (rc != H2DLP_OK) return rc;
+    std::unique_ptr<h2dlp_ctx> h(new (std::nothrow) h2dlp_ctx);
+    if (!h) return fail(H2DLP_ENOMEM, "host allocation failed");
+    try {
+        rc = plan_impl(h.get(), mesh, o);
+    } catch (const std::bad_alloc&) {
+        rc = fail(H2DLP_ENOMEM, "host allocation failed");
+    }
+    if (rc != H2DLP_OK) return rc;
+    *out = reinterpret_cast<h2dlp_handle>(h.release());
+    return H2DLP_OK;
+}
+
+int h2dlp_build_ex(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle* out) {
+    int rc = h2dlp_plan(mesh, o, out);
+    if (rc != H2DLP_OK) return rc;
+    std::unique_ptr<h2dlp_ctx> h(as_ctx(*out));
+    *out = nullptr;
+    int dev = o->device;
+    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(H2DLP_ENOTSUP, "no HIP device");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) return fail(H2DLP_ENOTSUP, "no such HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(H2DLP_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(H2DLP_ENOTSUP, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(dev) != hipSuccess) return fail(H2DLP_EDEVICE, "hipSetDevice failed");
+    h->device = dev;
+    try {
+        rc = materialize_impl(h.get(), static_cast<hipStream_t>(o->stream));
+    } catch (const HipError& e) {
+        rc = fail(H2DLP_EDEVICE, e.where + ": " + hipGetErrorString(e.err));
+    } catch (const std::bad_alloc&) {
+        rc = fail(H2DLP_ENOMEM, "device or host allocation failed");
+    }
+    if (rc != H2DLP_OK) {
+        h.reset();          // frees what was allocated on `dev`
+        hipSetDevice(cur);
+        return rc;
+    }
+    hipSetDevice(cur);
+    *out = reinterpret_cast<h2dlp_handle>(h.release());
+    return H2DLP_OK;
+}
+
+h2dlp_handle h2dlp_build(const h2dlp_mesh* mesh, int order, int leaf, double eta) {
+    h2dlp_options o;
+    h2dlp_default_options(&o);
+    o.order = order;
+    o.leaf = leaf;
+    o.eta = eta;
+    h2dlp_handle h = nullptr;
+    return h2dlp_build_ex(mesh, &o, &h) == H2DLP_OK ? h : nullptr;
+}
+
+int h2dlp_apply_ex(h2dlp_handle hh, const void* u1, void* u2, int nrhs, int io_dtype, void* stream, void* workspace,
+                   size_t workspace_bytes) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    if (!u1 || !u2) return fail(H2DLP_EINVAL, "u1 or u2 is NULL");
+    if (nrhs < 1) return fail(H2DLP_EINVAL, "nrhs must be >= 1");
+    if (!h->materialized) return fail(H2DLP_EINVAL, "handle comes from h2dlp_plan: nothing on the device");
+    if (io_dtype != H2DLP_IO_F64 && io_dtype != H2DLP_IO_F32) return fail(H2DLP_EINVAL, "unknown io dtype");
+    const size_t bytes = (io_dtype == H2DLP_IO_F32 ? 4 : 8) * size_t(nrhs) * size_t(h->S.n_nodes);
+    const char* a = static_cast<const char*>(u1);
+    const char* b = static_cast<const char*>(u2);
+    if (a < b + bytes && b < a + bytes) return fail(H2DLP_EINVAL, "u1 and u2 overlap");
+    void* ws = workspace;
+    if (ws == nullptr) ws = h->d_ws;
+    else if (workspace_bytes < h->ws_bytes) return fail(H2DLP_ENOMEM, "workspace smaller than h2dlp_stats.workspace_bytes");
+    int cur = 0;
+    hipGetDevice(&cur);
+    if (cur != h->device && hipSetDevice(h->device) != hipSuccess) return fail(H2DLP_EDEVICE, "hipSetDevice failed");
+    int rc;
+    try {
+        rc = apply_impl(h, u1, u2, nrhs, io_dtype, static_cast<hipStream_t>(stream), ws);
+    } catch (const HipError& e) {
+        rc = fail(H2DLP_EDEVICE, e.where + ": " + hipGetErrorString(e.err));
+    }
+    if (cur != h->device) hipSetDevice(cur);
+    return rc;
+}
+
+int h2dlp_apply(h2dlp_handle h, const double* u1, double* u2, int nrhs) {
+    return h2dlp_apply_ex(h, u1, u2, nrhs, H2DLP_IO_F64, nullptr, nullptr, 0);
+}
+
+int h2dlp_bytes(h2dlp_handle hh, size_t* resident, size_t* workspace) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    if (resident) *resident = size_t(h->st.bytes_resident);
+    if (workspace) *workspace = h->ws_bytes;
+    return H2DLP_OK;
+}
+
+int h2dlp_info(h2dlp_handle hh, h2dlp_stats* st) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h || !st) return fail(H2DLP_EINVAL, "handle or stats is NULL");
+    *st = h->st;
+    return H2DLP_OK;
+}
+
+int h2dlp_export_structure(h2dlp_handle hh, int64_t* perm, int64_t* clusters, double* boxes, int64_t* far,
+                           int64_t* near) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    const Structure& S = h->S;
+    if (perm)
+        for (int64_t q = 0; q < S.n_nodes; ++q) perm[q] = S.perm[q];
+    for (size_t c = 0; c < S.cl.size(); ++c) {
+        const Cluster& X = S.cl[c];
+        if (clusters) {
+            int64_t* r = clusters + 6 * c;
+            r[0] = X.begin; r[1] = X.end; r[2] = X.level; r[3] = X.parent; r[4] = X.child0; r[5] = X.child1;
+        }
+        if (boxes)
+            for (int a = 0; a < 3; ++a) { boxes[6 * c + a] = X.lo[a]; boxes[6 * c + 3 + a] = X.hi[a]; }
+    }
+    if (far)
+        for (size_t b = 0; b < S.far.size(); ++b) { far[2 * b] = S.far[b].first; far[2 * b + 1] = S.far[b].second; }
+    if (near)
+        for (size_t b = 0; b < S.near.size(); ++b) { near[2 * b] = S.near[b].first; near[2 * b + 1] = S.near[b].second; }
+    return H2DLP_OK;
+}
+
+int h2dlp_export_diagonal(h2dlp_handle hh, double* diag) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h || !diag) return fail(H2DLP_EINVAL, "handle or output is NULL");
+    if (!h->materialized) return fail(H2DLP_EINVAL, "handle comes from h2dlp_plan: nothing on the device");
+    std::vector<double> d(h->S.n_nodes);
+    if (hipSetDevice(h->device) != hipSuccess ||
+        hipMemcpy(d.data(), h->d_diag, sizeof(double) * d.size(), hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(H2DLP_EDEVICE, "copying the diagonal failed");
+    for (int64_t p = 0; p < h->S.n_nodes; ++p) diag[h->S.perm[p]] = d[p];
+    return H2DLP_OK;
+}
+
+void h2dlp_free(h2dlp_handle hh) { delete as_ctx(hh); }
+
+const char* h2dlp_last_error(void) { return g_last_error.c_str(); }
+
+int h2dlp_profile(h2dlp_handle hh, int enable) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    h->prof = enable != 0;
+    return H2DLP_OK;
+}
+
+int h2dlp_profile_read(h2dlp_handle hh, double* ms, int64_t* launches, int n_kinds, int reset) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    if (n_kinds < 0 || n_kinds > H2DLP_NKINDS) return fail(H2DLP_EINVAL, "n_kinds out of range");
+    for (auto& r : h->recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess)
+            return fail(H2DLP_EDEVICE, "reading profile events failed");
+        h->prof_ms[r.kind] += t;
+        h->prof_n[r.kind] += 1;
+        hipEventDestroy(r.a);
+        hipEventDestroy(r.b);
+    }
+    h->recs.clear();
+    for (int q = 0; q < n_kinds; ++q) {
+        if (ms) ms[q] = h->prof_ms[q];
+        if (launches) launches[q] = h->prof_n[q];
+    }
+    if (reset)
+        for (int q = 0; q < H2DLP_NKINDS; ++q) { h->prof_ms[q] = 0; h->prof_n[q] = 0; }
+    return H2DLP_OK;
+}
+
+}  // extern "C"

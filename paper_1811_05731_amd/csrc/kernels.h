@@ -1,0 +1,93 @@
+// Internal launch interface between the C ABI (api.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "layout.h"
+
+namespace h2dlp {
+
+enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2 };
+
+// ---------------------------------------------------------------- build (FP64 arithmetic)
+
+struct DevMesh {
+    const double* xyz;       // N x 3, node order
+    const int32_t* tri;      // T x 3
+    const int64_t* inc_off;  // node -> incident triangles (CSR)
+    const int32_t* inc_tri;
+    const int32_t* inc_loc;
+    const double* tgeo;      // T x 4: unit normal, area
+    const int32_t* perm;     // cluster position -> node
+};
+
+struct LeafDesc {   // one leaf cluster
+    int32_t pos;    // first cluster position
+    int32_t n;      // number of nodes
+    int32_t gid;    // cluster id in level order
+    int32_t pad;
+    int64_t a_off;  // offset of its block in the pool
+};
+
+struct FarDesc {    // one admissible block
+    int32_t t, s;   // cluster ids in level order
+    int64_t a_off;
+};
+
+struct NearDesc {   // one inadmissible leaf block
+    int32_t tpos, nt, spos, ns;
+    int64_t a_off;
+};
+
+hipError_t launch_tri_geometry(const double* xyz, const int32_t* tri, int64_t n_tris, double* tgeo, hipStream_t st);
+hipError_t launch_diagonal(DevMesh mesh, int64_t n_nodes, double* diag, hipStream_t st);
+hipError_t launch_build_v(DevMesh mesh, const double* boxes, int m, const LeafDesc* leaves, int64_t n_leaves,
+                          int prec, void* pool, hipStream_t st);
+hipError_t launch_build_wt(DevMesh mesh, const double* boxes, int m, const double* quad, int n_quad,
+                           const LeafDesc* leaves, int64_t n_leaves, int prec, void* pool, hipStream_t st);
+hipError_t launch_build_transfer(const double* boxes, const int32_t* parent, int64_t n_clusters, int m, int prec,
+                                 void* e, hipStream_t st);
+hipError_t launch_build_coupling(const double* boxes, int m, const FarDesc* far, int64_t n_far, int prec, void* pool,
+                                 hipStream_t st);
+hipError_t launch_build_near(DevMesh mesh, const NearDesc* near, int64_t n_near, int prec, void* pool,
+                             const int64_t* ring_off, const int32_t* ring_pos, double* ns_val, hipStream_t st);
+
+// ---------------------------------------------------------------- apply
+
+struct LeafEpilogue {           // u2 = y + D x (+ near-singular FP64 part), scattered to node order
+    const int32_t* perm;
+    const double* diag;         // by cluster position
+    const void* u1;             // (nrhs, N) of io type, already offset to this pass
+    void* u2;
+    int64_t n_nodes;
+    int32_t nr;                 // valid columns in this pass (<= 16)
+    int32_t io;                 // 0 FP64, 1 FP32
+    const int64_t* ns_off;      // by cluster position; NULL when there is no FP64 subset
+    const int32_t* ns_col;      // node index
+    const double* ns_val;
+};
+
+struct ProductArgs {
+    const ItemDesc* items;
+    int32_t n_items;
+    int32_t rt;                 // row tiles of the largest item, ceil(m/16)
+    const BlkDesc* blks;
+    const void* pool;
+    const void* x0;
+    const void* x1;
+    void* y;
+};
+
+hipError_t launch_permute(const void* u1, int io, int64_t n_nodes, int nr, const int32_t* perm, void* x, int prec,
+                          hipStream_t st);
+// prefer_rows: split the rows of one item over the 4 waves (else split its blocks)
+hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st);
+hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st);
+hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, const int32_t* child1, const void* e,
+                         void* xh, int m, int prec, hipStream_t st);
+hipError_t launch_downward(int32_t c_begin, int32_t c_end, const int32_t* parent, const void* e, void* yh, int m,
+                           int prec, hipStream_t st);
+
+}  // namespace h2dlp

@@ -1,0 +1,251 @@
+"""Python binding of the h2dlp C ABI (include/h2dlp.h): argument marshalling only.
+
+Every step of the operator runs in the HIP library ``libh2dlp.so``; this
+module only converts NumPy / torch arguments into pointers and sizes.  Device
+memory and streams come from PyTorch.  If the library is missing the import of
+this module fails: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libh2dlp.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
+FP64, FP32, BF16X3 = 0, 1, 2
+IO_F64, IO_F32 = 0, 1
+NKINDS = 6
+KIND_NAMES = ("permute", "leaf_forward", "upward", "coupling", "downward", "leaf_output")
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+
+
+class H2dlpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"h2dlp error {code}: {msg}")
+        self.code = code
+
+
+class _Mesh(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("xyz", ctypes.POINTER(ctypes.c_double)),
+                ("n_tris", ctypes.c_int64), ("tri", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int), ("leaf", ctypes.c_int), ("eta", ctypes.c_double),
+                ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("device", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_tris", ctypes.c_int64),
+                ("order", ctypes.c_int32), ("leaf", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("n_clusters", ctypes.c_int64), ("n_leaves", ctypes.c_int64),
+                ("n_far", ctypes.c_int64), ("n_near", ctypes.c_int64),
+                ("coupling_entries", ctypes.c_int64), ("near_entries", ctypes.c_int64),
+                ("nearsing_entries", ctypes.c_int64),
+                ("bytes_coupling", ctypes.c_int64), ("bytes_near", ctypes.c_int64),
+                ("bytes_bases", ctypes.c_int64), ("bytes_transfer", ctypes.c_int64),
+                ("bytes_other", ctypes.c_int64), ("bytes_resident", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("compression", ctypes.c_double)]
+
+
+EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
+            "h2dlp_bytes", "h2dlp_info", "h2dlp_export_structure", "h2dlp_export_diagonal", "h2dlp_free",
+            "h2dlp_last_error", "h2dlp_profile", "h2dlp_profile_read")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1811_05731_amd._build`")
+    try:                                   # share torch's HIP runtime when torch is present
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, D, V, L = ctypes.POINTER, ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_int64
+    lib.h2dlp_default_options.argtypes = [P(_Options)]
+    lib.h2dlp_default_options.restype = None
+    lib.h2dlp_build.argtypes = [P(_Mesh), I, I, D]
+    lib.h2dlp_build.restype = V
+    lib.h2dlp_build_ex.argtypes = [P(_Mesh), P(_Options), P(V)]
+    lib.h2dlp_build_ex.restype = I
+    lib.h2dlp_plan.argtypes = [P(_Mesh), P(_Options), P(V)]
+    lib.h2dlp_plan.restype = I
+    lib.h2dlp_apply.argtypes = [V, V, V, I]
+    lib.h2dlp_apply.restype = I
+    lib.h2dlp_apply_ex.argtypes = [V, V, V, I, I, V, V, ctypes.c_size_t]
+    lib.h2dlp_apply_ex.restype = I
+    lib.h2dlp_bytes.argtypes = [V, P(ctypes.c_size_t), P(ctypes.c_size_t)]
+    lib.h2dlp_bytes.restype = I
+    lib.h2dlp_info.argtypes = [V, P(_Stats)]
+    lib.h2dlp_info.restype = I
+    lib.h2dlp_export_structure.argtypes = [V, P(L), P(L), P(D), P(L), P(L)]
+    lib.h2dlp_export_structure.restype = I
+    lib.h2dlp_export_diagonal.argtypes = [V, P(D)]
+    lib.h2dlp_export_diagonal.restype = I
+    lib.h2dlp_free.argtypes = [V]
+    lib.h2dlp_free.restype = None
+    lib.h2dlp_last_error.argtypes = []
+    lib.h2dlp_last_error.restype = ctypes.c_char_p
+    lib.h2dlp_profile.argtypes = [V, I]
+    lib.h2dlp_profile.restype = I
+    lib.h2dlp_profile_read.argtypes = [V, P(D), P(L), I, I]
+    lib.h2dlp_profile_read.restype = I
+    return lib
+
+
+_lib = _load()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise H2dlpError(rc, _lib.h2dlp_last_error().decode())
+
+
+def default_options() -> dict:
+    o = _Options()
+    _lib.h2dlp_default_options(ctypes.byref(o))
+    return {f: getattr(o, f) for f, _ in _Options._fields_}
+
+
+@dataclass
+class Stats:
+    n_nodes: int
+    n_tris: int
+    order: int
+    leaf: int
+    k: int
+    precision: int
+    depth: int
+    n_clusters: int
+    n_leaves: int
+    n_far: int
+    n_near: int
+    coupling_entries: int
+    near_entries: int
+    nearsing_entries: int
+    bytes_coupling: int
+    bytes_near: int
+    bytes_bases: int
+    bytes_transfer: int
+    bytes_other: int
+    bytes_resident: int
+    workspace_bytes: int
+    compression: float
+
+
+def _ptr(t) -> int:
+    """Device pointer of a torch tensor (CUDA/HIP) after checking contiguity."""
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+class Operator:
+    """A built H2 boundary operator resident on one GPU (owns its device memory)."""
+
+    def __init__(self, xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0,
+                 precision="fp64", alpha: float = 0.1, device: int = -1, stream=None, plan_only: bool = False):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3:
+            raise ValueError("xyz must be N x 3 and tri T x 3")
+        mesh = _Mesh(xyz.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                     tri.shape[0], tri.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        opt = _Options()
+        _lib.h2dlp_default_options(ctypes.byref(opt))
+        opt.order, opt.leaf, opt.eta, opt.alpha, opt.device = order, leaf, eta, alpha, device
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opt.stream = stream
+        h = ctypes.c_void_p()
+        entry = _lib.h2dlp_plan if plan_only else _lib.h2dlp_build_ex
+        _check(entry(ctypes.byref(mesh), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self._free = _lib.h2dlp_free          # kept for interpreter shutdown
+        self.plan_only = plan_only
+        self.n_nodes = xyz.shape[0]
+        self.stats = self.info()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> Stats:
+        s = _Stats()
+        _check(_lib.h2dlp_info(self._h, ctypes.byref(s)))
+        return Stats(**{f: getattr(s, f) for f, _ in _Stats._fields_})
+
+    def bytes(self):
+        r, w = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(_lib.h2dlp_bytes(self._h, ctypes.byref(r), ctypes.byref(w)))
+        return r.value, w.value
+
+    def apply(self, u1, u2, nrhs: int | None = None, stream=None, workspace=None):
+        """u2 = M u1 for device tensors of shape (nrhs, N) (float64 or float32, same dtype)."""
+        import torch
+        if u1.dtype != u2.dtype or u1.dtype not in (torch.float64, torch.float32):
+            raise ValueError("u1 and u2 must both be float64 or both float32")
+        if u1.shape[-1] != self.n_nodes or u2.shape != u1.shape:
+            raise ValueError("u1, u2 must have shape (nrhs, N)")
+        nrhs = (u1.shape[0] if u1.dim() == 2 else 1) if nrhs is None else nrhs
+        io = IO_F64 if u1.dtype == torch.float64 else IO_F32
+        st = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        ws_ptr, ws_bytes = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
+        _check(_lib.h2dlp_apply_ex(self._h, _ptr(u1), _ptr(u2), int(nrhs), io, st, ws_ptr, ws_bytes))
+        return u2
+
+    def export_structure(self) -> dict:
+        s = self.stats
+        perm = np.empty(s.n_nodes, np.int64)
+        cl = np.empty((s.n_clusters, 6), np.int64)
+        boxes = np.empty((s.n_clusters, 6), np.float64)
+        far = np.empty((s.n_far, 2), np.int64)
+        near = np.empty((s.n_near, 2), np.int64)
+        P = lambda a, t: a.ctypes.data_as(ctypes.POINTER(t))  # noqa: E731
+        _check(_lib.h2dlp_export_structure(self._h, P(perm, ctypes.c_int64), P(cl, ctypes.c_int64),
+                                           P(boxes, ctypes.c_double), P(far, ctypes.c_int64),
+                                           P(near, ctypes.c_int64)))
+        return dict(perm=perm, begin=cl[:, 0], end=cl[:, 1], level=cl[:, 2], parent=cl[:, 3],
+                    child0=cl[:, 4], child1=cl[:, 5], box_lo=boxes[:, :3], box_hi=boxes[:, 3:],
+                    far=far, near=near)
+
+    def export_diagonal(self) -> np.ndarray:
+        d = np.empty(self.n_nodes, np.float64)
+        _check(_lib.h2dlp_export_diagonal(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return d
+
+    def profile(self, enable: bool = True):
+        _check(_lib.h2dlp_profile(self._h, int(enable)))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        ms = (ctypes.c_double * NKINDS)()
+        n = (ctypes.c_int64 * NKINDS)()
+        _check(_lib.h2dlp_profile_read(self._h, ms, n, NKINDS, int(reset)))
+        return {KIND_NAMES[q]: (ms[q], n[q]) for q in range(NKINDS)}
+
+
+def plan(xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64", alpha: float = 0.1):
+    """Host-only structure and byte counts (no GPU needed)."""
+    return Operator(xyz, tri, order, leaf, eta, precision, alpha, plan_only=True)
+
+
+def last_error() -> str:
+    return _lib.h2dlp_last_error().decode()
+
+
+def library():
+    return _lib

@@ -1,0 +1,124 @@
+"""The C ABI without a GPU: symbols, argument checks, host-only planning and
+structure identity with the oracle (cluster tree, boxes, block lists)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import h2
+from paper_1811_05731_amd import h2dlp
+from workloads import cases, meshes
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "h2dlp.h")
+
+
+def test_every_declared_symbol_is_exported():
+    names = set(re.findall(r"\b(h2dlp_[a-z_]+)\s*\(", open(HEADER).read()))
+    assert len(names) >= 14
+    lib = ctypes.CDLL(h2dlp.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert set(h2dlp.EXPORTED) == names
+
+
+def test_default_options():
+    o = h2dlp.default_options()
+    assert (o["order"], o["leaf"], o["eta"], o["precision"], o["alpha"], o["device"]) == (4, 32, 2.0, 0, 0.1, -1)
+
+
+def _plan_rc(xyz, tri, **kw):
+    try:
+        h2dlp.plan(xyz, tri, **kw)
+        return 0
+    except h2dlp.H2dlpError as e:
+        return e.code
+
+
+def test_argument_errors():
+    xyz, tri = meshes.icosphere(2)
+    assert _plan_rc(xyz, tri, order=0) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, order=9) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, leaf=0) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, leaf=65) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, eta=0.0) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, eta=float("nan")) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, alpha=-0.1) == h2dlp.EINVAL
+    lib = h2dlp.library()
+    out = ctypes.c_void_p()
+    opt = h2dlp._Options()
+    lib.h2dlp_default_options(ctypes.byref(opt))
+    assert lib.h2dlp_plan(None, ctypes.byref(opt), ctypes.byref(out)) == h2dlp.EINVAL
+    assert lib.h2dlp_build(None, 4, 32, 2.0) is None
+    assert lib.h2dlp_apply(None, None, None, 1) == h2dlp.EINVAL
+    assert lib.h2dlp_info(None, None) == h2dlp.EINVAL
+    assert "NULL" in h2dlp.last_error()
+
+
+def test_mesh_errors():
+    xyz, tri = meshes.icosphere(2)
+    bad = tri.copy(); bad[0] = bad[0][[0, 2, 1]]
+    assert _plan_rc(xyz, bad) == h2dlp.EINVAL and "orientation" in h2dlp.last_error()
+    assert _plan_rc(xyz, tri[1:]) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri[:, [0, 2, 1]]) == h2dlp.EINVAL and "volume" in h2dlp.last_error()
+    bad = tri.copy(); bad[5, 2] = bad[5, 0]
+    assert _plan_rc(xyz, bad) == h2dlp.EINVAL and "degenerate" in h2dlp.last_error()
+    bad = tri.copy(); bad[0, 0] = xyz.shape[0]
+    assert _plan_rc(xyz, bad) == h2dlp.EINVAL and "range" in h2dlp.last_error()
+    dup = xyz.copy(); dup[7] = dup[3]
+    assert _plan_rc(dup, tri) == h2dlp.EINVAL
+    nan = xyz.copy(); nan[2, 1] = np.nan
+    assert _plan_rc(nan, tri) == h2dlp.EINVAL
+
+
+def test_apply_on_plan_handle_is_rejected():
+    xyz, tri = meshes.icosphere(2)
+    p = h2dlp.plan(xyz, tri)
+    lib = h2dlp.library()
+    buf = (ctypes.c_double * (2 * xyz.shape[0]))()
+    assert lib.h2dlp_apply(p.handle, buf, ctypes.byref(buf, 8 * xyz.shape[0]), 1) == h2dlp.EINVAL
+
+
+def _same_structure(xyz, tri, order, leaf, eta):
+    lib_s = h2dlp.plan(xyz, tri, order=order, leaf=leaf, eta=eta).export_structure()
+    ora_s = h2.H2Oracle(xyz, tri, order=order, leaf=leaf, eta=eta).export_structure()
+    for key in ora_s:
+        assert np.array_equal(np.asarray(ora_s[key]), np.asarray(lib_s[key])), key
+
+
+@pytest.mark.parametrize("mesh,leaf,eta", [
+    (lambda: meshes.icosphere(4, 0.01, 0), 32, 2.0),
+    (lambda: meshes.icosphere(5, 0.01, 0), 64, 2.0),
+    (lambda: meshes.icosphere(3, 0.0, 0), 16, 1.0),                 # unjittered: many ties
+    (lambda: meshes.cuboid(200.0, 200.0, 20.0, 5.0, 0.5, 0), 64, 2.0),  # flat faces: inflated boxes
+    (lambda: meshes.torus(1.0, 0.3, 64, 16), 32, 3.0),
+])
+def test_structure_identical_to_oracle(mesh, leaf, eta):
+    xyz, tri = mesh()
+    _same_structure(xyz, tri, 4, leaf, eta)
+
+
+def test_plan_sizes():
+    xyz, tri = meshes.icosphere(4, 0.01, 0)
+    s = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0).stats
+    ora = h2.H2Oracle(xyz, tri, order=4, leaf=32, eta=2.0).counts()
+    assert (s.n_clusters, s.n_leaves, s.n_far, s.n_near, s.near_entries) == \
+        (ora["clusters"], ora["leaves"], ora["far"], ora["near"], ora["near_entries"])
+    assert s.coupling_entries == s.n_far * 64 * 64
+    assert s.bytes_coupling == 8 * s.coupling_entries
+    s32 = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, precision="fp32").stats
+    assert s32.bytes_coupling == 4 * s.coupling_entries
+    assert 10 * xyz.shape[0] < s32.nearsing_entries < 25 * xyz.shape[0]   # the 2-ring, ~18 per node
+    r, w = h2dlp.plan(xyz, tri).bytes()
+    assert w > 0 and r > w
+
+
+def test_build_without_gpu_reports_no_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    xyz, tri = meshes.icosphere(2)
+    with pytest.raises(h2dlp.H2dlpError) as e:
+        h2dlp.Operator(xyz, tri)
+    assert e.value.code in (h2dlp.ENOTSUP, h2dlp.EDEVICE)
