@@ -32,15 +32,21 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Mfma;
+// A operand: lane l holds A[l % 16][l / 16]; B operand: B[l / 16][l % 16].
+// The 16 x 16 result comes back as 4 values per lane, column l % 16; the row
+// of value v in lane group g = l / 16 differs by type: 4 g + v for f32, g + 4 v
+// for f64 (measured on gfx950, pinned by the GPU parity tests).
 template <>
 struct Mfma<float> {
     typedef f32x4 acc;
     static __device__ inline acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int g, int v) { return 4 * g + v; }
 };
 template <>
 struct Mfma<double> {
     typedef f64x4 acc;
     static __device__ inline acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int g, int v) { return g + 4 * v; }
 };
 
 // Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous
@@ -181,7 +187,7 @@ __global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogu
     for (int r = 0; r < RTW; ++r) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 16 * (rg * RTW + r) + 4 * (lane >> 4) + v;
+            const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
             if (row >= M) continue;
             if (EPI == EPI_STORE) {
                 static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + q] = acc[r][v];
