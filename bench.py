@@ -1,0 +1,264 @@
+"""Benchmark of the H2 boundary double-layer matvec u2 = (K + D) u1 on one MI355X.
+
+One step = one apply of the whole hot path (permute, leaf forward, upward
+transfers, coupling, downward transfers, leaf backward + near field + diagonal)
+to 16 right-hand sides on the level-8 icosphere (655362 boundary nodes), order
+5, leaf 64, eta 2.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  `value` is boundary degrees of freedom per second
+(N * nrhs / t_apply / 1e9).  `roofline` is computed for the dominant kernel
+(the coupling products) from its HIP-event time inside the timed region.
+`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H² DLP matvec boundary GDOF/s + %HBM roofline; serve p50/p99 at 1e-6 rel err"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1811_05731_amd/csrc/apply_kernels.hip", "paper_1811_05731_amd/csrc/layout.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "coupling_sphere_l8_traffic.json")
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def workload(name: str):
+    from workloads import cases
+    c = cases.CASES[name]
+    xyz, tri = cases.mesh_of(c.mesh)
+    return c, xyz, tri
+
+
+def coupling_alg_bytes(st, elem: int) -> int:
+    """Algorithmic bytes of one coupling launch: every S_ts once, xhat read once, yhat written once."""
+    return st.coupling_entries * elem + 2 * st.n_clusters * st.k * 16 * elem
+
+
+def apply_alg_bytes(st, elem: int, n_nodes: int, nrhs: int, io_elem: int = 8) -> int:
+    """Algorithmic bytes of one apply: the stored operator once, plus compulsory vectors."""
+    operator = st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer
+    vectors = 8 * n_nodes + 4 * n_nodes + 2 * io_elem * n_nodes * nrhs + 2 * 2 * st.n_clusters * st.k * 16 * elem
+    return operator + vectors
+
+
+def time_path(op, d_u1, d_u2, steps: int, warmup: int, profile: bool):
+    import torch
+    for _ in range(warmup):
+        op.apply(d_u1, d_u2)
+    torch.cuda.synchronize()
+    if profile:
+        op.profile(True)
+        op.profile_read(reset=True)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(steps):
+        op.apply(d_u1, d_u2)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    kernels = None
+    if profile:
+        kernels = op.profile_read(reset=True)
+        op.profile(False)
+    return ms, kernels
+
+
+def cpu_baseline(xyz, tri, case, nrhs: int, frac: float = 0.01, seed: int = 7) -> dict:
+    """The oracle's apply timed on a bounded sample of the same workload.
+
+    The oracle's matvec is a loop over work items (leaves, clusters, far
+    blocks, near blocks).  A seeded sample `frac` of each kind of item is
+    timed through the oracle's own routines, with the coupling matrices
+    generated on the fly as the oracle does at this size; the full-apply time
+    is the per-item time times the item counts.  Pieces the oracle builds once
+    (bases, transfers, near blocks) are built outside the timed region.
+    """
+    from threadpoolctl import threadpool_limits
+
+    from oracle import h2
+
+    t_build0 = time.perf_counter()
+    H = h2.H2Oracle(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, cache_coupling=False)
+    t_struct = time.perf_counter() - t_build0
+    rng = np.random.default_rng(seed)
+    C = H.n_clusters
+    leaves = np.where(H.child0 < 0)[0]
+    inner = np.where(H.child0 >= 0)[0]
+    nonroot = np.arange(1, C)
+    pick = lambda a: rng.choice(a, max(1, int(round(frac * len(a)))), replace=False)  # noqa: E731
+    s_leaf, s_inner, s_far, s_near, s_down = pick(leaves), pick(inner), pick(np.arange(len(H.far))), \
+        pick(np.arange(len(H.near))), pick(nonroot)
+    k = H.k
+    x = rng.normal(size=(xyz.shape[0], nrhs))
+    xh = rng.normal(size=(k, nrhs))
+    # build-time pieces of the sampled items (untimed)
+    for c in s_leaf:
+        H.W(c), H.V(c)
+    for c in s_inner:
+        H.E(H.child0[c]), H.E(H.child1[c])
+    for c in s_down:
+        H.E(c)
+    for b in s_near:
+        H.K_near(*H.near[b])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for c in s_leaf:
+            _ = H.W(c).T @ x[H.nodes(c)]
+            _ = H.V(c) @ xh
+        t_leaf = (time.perf_counter() - t0) / len(s_leaf)
+        t0 = time.perf_counter()
+        for c in s_inner:
+            _ = H.E(H.child0[c]).T @ xh + H.E(H.child1[c]).T @ xh
+        t_up = (time.perf_counter() - t0) / len(s_inner)
+        t0 = time.perf_counter()
+        for c in s_down:
+            _ = H.E(c) @ xh
+        t_down = (time.perf_counter() - t0) / len(s_down)
+        t0 = time.perf_counter()
+        for b in s_far:
+            t, s = H.far[b]
+            _ = H.S(t, s) @ xh
+        t_far = (time.perf_counter() - t0) / len(s_far)
+        t0 = time.perf_counter()
+        for b in s_near:
+            t, s = H.near[b]
+            _ = H.K_near(t, s) @ x[H.nodes(s)]
+        t_near = (time.perf_counter() - t0) / len(s_near)
+        t0 = time.perf_counter()
+        _ = H.D[:, None] * x
+        t_diag = time.perf_counter() - t0
+    total = (t_leaf * len(leaves) + t_up * len(inner) + t_down * len(nonroot) + t_far * len(H.far)
+             + t_near * len(H.near) + t_diag)
+    n = xyz.shape[0]
+    return {
+        "value": n * nrhs / total / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+        "sample": (f"{frac:.0%} of each item kind of the same operator, seed {seed}: {len(s_leaf)} leaves, "
+                   f"{len(s_inner)} upward and {len(s_down)} downward transfers, {len(s_far)} far blocks "
+                   f"(coupling generated on the fly), {len(s_near)} near blocks; full-apply time = per-item "
+                   f"time x item counts; NumPy FP64, BLAS limited to one thread"),
+        "est_apply_s": total, "oracle_structure_s": round(t_struct, 2),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="sphere_l8")
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-variants", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported (the apply shards by target "
+              "rows with one all-gather of u1; that path is a design, not built here)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1811_05731_amd import h2dlp
+    from workloads import rhs
+
+    case, xyz, tri = workload(args.workload)
+    n = xyz.shape[0]
+    nrhs = case.nrhs
+    u1 = rhs.normal_rhs(n, nrhs, 0)
+    dev = torch.device("cuda:0")
+    d_u1 = torch.tensor(u1, device=dev)
+    d_u2 = torch.empty_like(d_u1)
+
+    t0 = time.perf_counter()
+    op = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=args.precision, device=0)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    st = op.stats
+    elem = 8 if args.precision == "fp64" else 4
+    print(f"# built {case.name} {args.precision}: N={n} clusters={st.n_clusters} far={st.n_far} near={st.n_near} "
+          f"resident={st.bytes_resident / 1e9:.2f} GB in {build_s:.1f} s", file=sys.stderr, flush=True)
+
+    ms, kernels = time_path(op, d_u1, d_u2, args.steps, args.warmup, profile=True)
+    u2_main = d_u2.cpu().numpy()
+    value = n * nrhs / (ms * 1e-3) / 1e9
+    cpl_ms, cpl_n = kernels["coupling"]
+    cpl_avg_ms = cpl_ms / max(cpl_n, 1)
+    b_cpl = coupling_alg_bytes(st, elem)
+    achieved = b_cpl / (cpl_avg_ms * 1e-3) / 1e9
+    b_apply = apply_alg_bytes(st, elem, n, nrhs)
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("kernel_hash") == kernel_hash() and rec.get("precision") == args.precision \
+                and rec.get("workload") == args.workload:
+            traffic = rec.get("bytes_per_launch")
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": f"{case.name}: icosphere level {case.mesh.level}, {n} boundary nodes, "
+                               f"{tri.shape[0]} triangles, radial jitter +-{case.mesh.jitter:g}, order {case.order}, "
+                               f"leaf {case.leaf}, eta {case.eta:g}, {nrhs} N(0,1) right-hand sides",
+                   "nodes": n, "rhs": nrhs, "order": case.order, "leaf": case.leaf, "eta": case.eta,
+                   "precision": args.precision},
+        "roofline": {"bound": "hbm", "kernel": "coupling", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "alg_bytes_per_launch": b_cpl, "avg_launch_ms": round(cpl_avg_ms, 4)},
+        "apply_hbm_frac": round(b_apply / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "apply_alg_bytes": b_apply,
+        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kernels.items()},
+        "operator": {"clusters": st.n_clusters, "far_blocks": st.n_far, "near_blocks": st.n_near,
+                     "coupling_bytes": st.bytes_coupling, "near_bytes": st.bytes_near,
+                     "resident_bytes": st.bytes_resident, "compression": round(st.compression, 5),
+                     "build_s": round(build_s, 2)},
+        "kernel_hash": kernel_hash(),
+    }
+    op.close()
+
+    if not args.no_variants and args.precision == "fp32":
+        op64 = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision="fp64", device=0)
+        ms64, k64 = time_path(op64, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=True)
+        u2_64 = d_u2.cpu().numpy()
+        err = np.max(np.linalg.norm(u2_main - u2_64, axis=1) / np.linalg.norm(u2_64, axis=1))
+        c64_ms, c64_n = k64["coupling"]
+        out["variants"] = {"fp64": {
+            "value": round(n * nrhs / (ms64 * 1e-3) / 1e9, 4), "ms_per_step": round(ms64, 4),
+            "coupling_GBps": round(coupling_alg_bytes(op64.stats, 8) / (c64_ms / max(c64_n, 1) * 1e-3) / 1e9, 1),
+            "apply_hbm_frac": round(apply_alg_bytes(op64.stats, 8, n, nrhs) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+        out["fp32_vs_fp64_gpu_rel_err"] = float(f"{err:.3e}")
+        op64.close()
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)        # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = a.numel() * 4
+
+    if not args.no_cpu:
+        print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(xyz, tri, case, nrhs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
