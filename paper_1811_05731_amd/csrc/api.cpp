@@ -108,6 +108,7 @@ struct h2dlp_ctx {
     // device
     std::vector<DevBuf> bufs;
     int32_t* d_perm = nullptr;
+    int32_t* d_iperm = nullptr;
     double* d_diag = nullptr;
     int32_t* d_child0 = nullptr;
     int32_t* d_child1 = nullptr;
@@ -123,10 +124,10 @@ struct h2dlp_ctx {
     ItemDesc* d_items_leaf = nullptr;
     BlkDesc* d_blks_leaf = nullptr;
     int64_t* d_ns_off = nullptr;
-    int32_t* d_ns_col = nullptr;
+    int32_t* d_ns_pos = nullptr;
     double* d_ns_val = nullptr;
     void* d_ws = nullptr;
-    size_t ws_bytes = 0, ws_x = 0, ws_xh = 0;
+    size_t ws_bytes = 0, ws_x = 0, ws_x64 = 0, ws_y64 = 0, ws_xh = 0;
     int32_t n_items_fwd = 0, n_items_cpl = 0, n_items_leaf = 0;
     int32_t rt_leaf = 1;
     bool materialized = false;
@@ -243,6 +244,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     for (size_t q = 0; q < leaf_pre.size(); ++q) {
         const Cluster& X = S.cl[leaf_pre[q]];
         const int32_t g = h->gid_of_pre[leaf_pre[q]];
+        off_wt = align_block(off_wt);
         h->leaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), g, 0, off_wt};
         h->items_fwd.push_back(ItemDesc{g * k, k, int32_t(h->blks_fwd.size()), int32_t(h->blks_fwd.size() + 1)});
         h->blks_fwd.push_back(BlkDesc{off_wt, int32_t(X.size()), int32_t(X.begin)});
@@ -258,6 +260,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         std::sort(lst.begin(), lst.end());
         h->items_cpl.push_back(ItemDesc{g * k, k, int32_t(h->blks_cpl.size()), int32_t(h->blks_cpl.size() + lst.size())});
         for (int32_t s : lst) {
+            off_s = align_block(off_s);
             h->fars.push_back(FarDesc{g, s, off_s});
             h->blks_cpl.push_back(BlkDesc{off_s, k, s * k});
             off_s += int64_t(k) * k;
@@ -275,11 +278,13 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         std::sort(lst.begin(), lst.end(), [&](int32_t a, int32_t b) { return S.cl[a].begin < S.cl[b].begin; });
         h->items_leaf.push_back(ItemDesc{int32_t(X.begin), int32_t(X.size()), int32_t(h->blks_leaf.size()),
                                          int32_t(h->blks_leaf.size() + 1 + lst.size())});
+        off_l = align_block(off_l);
         h->vleaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), h->gid_of_pre[t], 0, off_l};
         h->blks_leaf.push_back(BlkDesc{off_l, k, SRC1 | (h->gid_of_pre[t] * k)});
         off_l += int64_t(X.size()) * k;
         for (int32_t s : lst) {
             const Cluster& Y = S.cl[s];
+            off_l = align_block(off_l);
             h->nears.push_back(NearDesc{int32_t(X.begin), int32_t(X.size()), int32_t(Y.begin), int32_t(Y.size()), off_l});
             h->blks_leaf.push_back(BlkDesc{off_l, int32_t(Y.size()), int32_t(Y.begin)});
             off_l += int64_t(X.size()) * Y.size();
@@ -295,9 +300,13 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     h->off_l = off_l;
 
     const size_t e = h->elem;
+    // workspace of one 16-column pass: x (operator precision), x64 (FP32 path),
+    // y64, xhat and yhat
     h->ws_x = align_up(e * size_t(N) * RHS_TILE);
+    h->ws_x64 = fp64 ? 0 : align_up(8 * size_t(N) * RHS_TILE);
+    h->ws_y64 = align_up(8 * size_t(N) * RHS_TILE);
     h->ws_xh = align_up(e * size_t(C) * k * RHS_TILE);
-    h->ws_bytes = h->ws_x + 2 * h->ws_xh;
+    h->ws_bytes = h->ws_x + h->ws_x64 + h->ws_y64 + 2 * h->ws_xh;
 
     h2dlp_stats& st = h->st;
     st = h2dlp_stats{};
@@ -312,20 +321,20 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     st.n_leaves = h->n_leaves;
     st.n_far = int64_t(S.far.size());
     st.n_near = int64_t(S.near.size());
-    st.coupling_entries = off_s;
+    st.coupling_entries = int64_t(S.far.size()) * k * k;
     st.near_entries = near_entries;
     st.nearsing_entries = fp64 ? 0 : int64_t(S.ring_pos.size());
-    st.bytes_coupling = int64_t(e * size_t(off_s));
+    st.bytes_coupling = int64_t(e * size_t(st.coupling_entries));
     st.bytes_near = int64_t(e * size_t(near_entries));
     if (!fp64) st.bytes_near += int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8));
-    st.bytes_bases = int64_t(e * size_t(off_wt + N * int64_t(k)));
+    st.bytes_bases = int64_t(e * size_t(2 * N * int64_t(k)));
     st.bytes_transfer = int64_t(e * size_t(C) * 3 * m * m);
-    st.bytes_other = int64_t(N * 4 + 3 * int64_t(C) * 4 + N * 8 +
+    st.bytes_other = int64_t(N * 8 + 3 * int64_t(C) * 4 + N * 8 +
                              (h->items_fwd.size() + h->items_cpl.size() + h->items_leaf.size()) * sizeof(ItemDesc) +
                              (h->blks_fwd.size() + h->blks_cpl.size() + h->blks_leaf.size()) * sizeof(BlkDesc));
     st.workspace_bytes = int64_t(h->ws_bytes);
-    st.bytes_resident = st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer + st.bytes_other +
-                        st.workspace_bytes;
+    st.bytes_resident = int64_t(e * size_t(off_wt + off_s + off_l)) + st.bytes_transfer + st.bytes_other +
+                        st.workspace_bytes + (fp64 ? 0 : int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8)));
     const double h2_bytes = double(st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer);
     st.compression = 1.0 - h2_bytes / (8.0 * double(N) * double(N));
     return H2DLP_OK;
@@ -341,7 +350,9 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     const size_t e = h->elem;
     int64_t kept = 0, scratch = 0;
     std::vector<int32_t> perm32(S.perm.begin(), S.perm.end());
+    std::vector<int32_t> iperm32(S.iperm.begin(), S.iperm.end());
     h->d_perm = h->upload(perm32, &kept, stream);
+    h->d_iperm = h->upload(iperm32, &kept, stream);
     h->d_child0 = h->upload(h->child0, &kept, stream);
     h->d_child1 = h->upload(h->child1, &kept, stream);
     h->d_parent = h->upload(h->parent, &kept, stream);
@@ -358,10 +369,8 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_blks_leaf = h->upload(h->blks_leaf, &kept, stream);
     if (!fp64) {
         h->d_ns_off = h->upload(S.ring_off, &kept, stream);
-        std::vector<int32_t> col(S.ring_pos.size());
-        for (size_t q = 0; q < col.size(); ++q) col[q] = S.perm[S.ring_pos[q]];
-        h->d_ns_col = h->upload(col, &kept, stream);
-        const size_t nb = sizeof(double) * std::max<size_t>(1, col.size());
+        h->d_ns_pos = h->upload(S.ring_pos, &kept, stream);
+        const size_t nb = sizeof(double) * std::max<size_t>(1, S.ring_pos.size());
         h->d_ns_val = h->alloc<double>(nb, &kept);
         check(hipMemsetAsync(h->d_ns_val, 0, nb, stream), "clear near-singular values");
     }
@@ -380,7 +389,6 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     LeafDesc* d_vleaves = tmp(h->upload(h->vleaves, &scratch, stream));
     FarDesc* d_far = tmp(h->upload(h->fars, &scratch, stream));
     NearDesc* d_near = tmp(h->upload(h->nears, &scratch, stream));
-    int32_t* d_ring_pos = fp64 ? nullptr : tmp(h->upload(S.ring_pos, &scratch, stream));
 
     DevMesh dm{d_xyz, d_tri, d_inc_off, d_inc_tri, d_inc_loc, d_tgeo, h->d_perm};
     check(launch_tri_geometry(d_xyz, d_tri, T, d_tgeo, stream), "triangle geometry");
@@ -392,7 +400,8 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     check(launch_build_transfer(d_boxes, h->d_parent, C, m, h->prec, h->d_e, stream), "transfer");
     check(launch_build_coupling(d_boxes, m, d_far, int64_t(h->fars.size()), h->prec, h->d_pool_s, stream), "coupling");
     check(launch_build_near(dm, d_near, int64_t(h->nears.size()), h->prec, h->d_pool_leaf,
-                            fp64 ? nullptr : h->d_ns_off, d_ring_pos, fp64 ? nullptr : h->d_ns_val, stream),
+                            fp64 ? nullptr : h->d_ns_off, fp64 ? nullptr : h->d_ns_pos, fp64 ? nullptr : h->d_ns_val,
+                            stream),
           "near field");
     check(hipStreamSynchronize(stream), "build synchronize");
     for (void* p : temp) h->release(p);
@@ -426,8 +435,10 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
     const int m = h->m, k = h->k, prec = h->prec;
     char* base = static_cast<char*>(ws);
     void* x = base;
-    void* xh = base + h->ws_x;
-    void* yh = base + h->ws_x + h->ws_xh;
+    double* x64 = h->ws_x64 ? reinterpret_cast<double*>(base + h->ws_x) : static_cast<double*>(x);
+    double* y64 = reinterpret_cast<double*>(base + h->ws_x + h->ws_x64);
+    void* xh = base + h->ws_x + h->ws_x64 + h->ws_y64;
+    void* yh = static_cast<char*>(xh) + h->ws_xh;
     const size_t io_elem = io == H2DLP_IO_F32 ? 4 : 8;
     for (int c0 = 0; c0 < nrhs; c0 += RHS_TILE) {
         const int nr = std::min(RHS_TILE, nrhs - c0);
@@ -435,7 +446,7 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         void* u2p = static_cast<char*>(u2) + io_elem * size_t(c0) * N;
         hipEvent_t ev = nullptr;
         rec_begin(h, s, &ev);
-        check(launch_permute(u1p, io, N, nr, h->d_perm, x, prec, s), "permute");
+        check(launch_permute(u1p, io, N, nr, h->d_iperm, x, h->ws_x64 ? x64 : nullptr, prec, s), "permute");
         rec_end(h, s, 0, ev);
 
         ProductArgs fwd{h->d_items_fwd, h->n_items_fwd, (k + 15) / 16, h->d_blks_fwd, h->d_pool_wt, x, nullptr, xh};
@@ -462,9 +473,10 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         }
 
         ProductArgs leaf{h->d_items_leaf, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
-        LeafEpilogue epi{h->d_perm, h->d_diag, u1p, u2p, N, nr, io, h->d_ns_off, h->d_ns_col, h->d_ns_val};
+        LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
         rec_begin(h, s, &ev);
         check(launch_product_leaf(leaf, epi, prec, s), "leaf output");
+        check(launch_unpermute(y64, io, N, nr, h->d_iperm, u2p, s), "unpermute");
         rec_end(h, s, 5, ev);
     }
     return H2DLP_OK;

@@ -1,20 +1,22 @@
 // Apply kernels: u2 = (K_H2 + D) u1, 16 right-hand sides per pass.
 //
-//   permute      x = P u1 (node order -> cluster order), cast to the operator precision
+//   permute      x = P u1 (node order -> cluster order) in the operator
+//                precision, plus an FP64 copy x64 on the FP32 path
 //   product      grouped block products Y_item = sum_b A_b X_b on MFMA 16x16x4
 //                (FP32 or FP64), used three times:
 //                  leaf forward   xhat_s = W_s^T x|_s                     (one block per leaf)
 //                  coupling       yhat_t = sum_{s admissible} S_ts xhat_s  (one item per cluster)
 //                  leaf output    y|_t = V_t yhat_t + sum_{s near} K_ts x|_s, then
-//                                 u2 = y + D x (+ FP64 near-singular part), scattered
+//                                 y64 = y + D x64 (+ FP64 near-singular part), cluster order
 //   upward       xhat_t = sum_c E_c^T xhat_c     (Kronecker mode products, per level)
 //   downward     yhat_c += E_c yhat_parent        (per level)
+//   unpermute    u2 = P^T y64
 //
 // The product kernel owns every output row it writes (no atomics): a
 // workgroup of 4 waves takes one item, the waves split its blocks (or its row
 // tiles), and partial sums meet in LDS in a fixed order, so results are
-// bitwise reproducible.  A blocks are streamed straight from HBM into MFMA
-// operand registers (layout.h); X rows come through L2.
+// bitwise reproducible.  A blocks stream from HBM straight into MFMA operand
+// registers, four k-steps per lane load (layout.h); X rows come through L2.
 #include <hip/hip_runtime.h>
 
 #include "kernels.h"
@@ -25,26 +27,29 @@ namespace {
 
 constexpr int kWaves = 4;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kUnroll = 4;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <typename T>
-struct Mfma;
 // A operand: lane l holds A[l % 16][l / 16]; B operand: B[l / 16][l % 16].
 // The 16 x 16 result comes back as 4 values per lane, column l % 16; the row
 // of value v in lane group g = l / 16 differs by type: 4 g + v for f32, g + 4 v
 // for f64 (measured on gfx950, pinned by the GPU parity tests).
+template <typename T>
+struct Mfma;
 template <>
 struct Mfma<float> {
     typedef f32x4 acc;
+    typedef f32x4 vec4;
+    static constexpr int kGroupUnroll = 2;
     static __device__ inline acc mma(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     static __device__ inline int row(int g, int v) { return 4 * g + v; }
 };
 template <>
 struct Mfma<double> {
     typedef f64x4 acc;
+    typedef f64x4 vec4;
+    static constexpr int kGroupUnroll = 1;
     static __device__ inline acc mma(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
     static __device__ inline int row(int g, int v) { return g + 4 * v; }
 };
@@ -59,87 +64,94 @@ __device__ inline int xcd_item(int n_items) {
 
 enum { EPI_STORE = 0, EPI_LEAF = 1 };
 
-// Accumulate sum_b A_b X_b of one item into acc[RTW] (row tiles rg*RTW ...).
-// Inside a full k-step the chunk of row tile rt starts at 64 rt and lane l
-// reads entry kk*rv + i (= l for a full tile); each lane keeps that 32-bit
-// offset per row tile, so a load is uniform base + lane offset.  Lanes outside
-// a partial tile read entry 0 of the chunk and discard it; tiles past the
-// item's rows multiply zeros (branch-free MFMA issue).
-template <typename T>
-__device__ inline T ld(const unsigned char* base, unsigned byte_off) {
-    return *reinterpret_cast<const T*>(base + byte_off);   // SGPR base + 32-bit VGPR offset
+template <typename V>
+__device__ inline V ld(const unsigned char* base, unsigned byte_off) {
+    return *reinterpret_cast<const V*>(base + byte_off);   // SGPR base + 32-bit VGPR offset
 }
 
+// Accumulate sum_b A_b X_b of one item into acc[RTW] (row tiles rg*RTW ...).
+// Each lane keeps, per row tile, the byte offset of its 4-entry vector inside
+// a 16-column group chunk; lanes outside a partial tile read the chunk start
+// and discard it; tiles past the item's rows multiply zeros (branch-free).
 template <typename T, int RTW>
 __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict__ blks, const T* __restrict__ pool,
                                   const T* __restrict__ x0, const T* __restrict__ x1, int rg, int bg, int nbg,
                                   typename Mfma<T>::acc* acc) {
+    typedef typename Mfma<T>::vec4 vec4;
+    constexpr int GU = Mfma<T>::kGroupUnroll;
     constexpr unsigned E = sizeof(T);
     const unsigned lane = threadIdx.x & 63;
     const unsigned i = lane & 15, kk = lane >> 4;
     const int M = it.m;
     const int RT = (M + 15) >> 4;
-    unsigned off[RTW];   // byte offset of this lane's entry of row tile r inside a full k-step
+    unsigned goff[RTW];
     bool ok[RTW];
 #pragma unroll
     for (int r = 0; r < RTW; ++r) {
         const int rt = rg * RTW + r;
         const unsigned rv = unsigned(M - 16 * rt < 16 ? M - 16 * rt : 16);
         ok[r] = rt < RT && i < rv;
-        off[r] = ok[r] ? E * (64u * rt + kk * rv + i) : 0u;
+        goff[r] = ok[r] ? E * (256u * rt + 4u * (kk * rv + i)) : 0u;
     }
     const unsigned xoff = E * lane;
+    const unsigned gstep = E * 16u * unsigned(M);   // bytes of one 16-column group
     for (int b = it.blk_begin + bg; b < it.blk_end; b += nbg) {
         const BlkDesc d = blks[b];
-        const unsigned char* Ak = reinterpret_cast<const unsigned char*>(pool + d.a_off);
-        const unsigned char* Xk = reinterpret_cast<const unsigned char*>(
+        const unsigned char* Ab = reinterpret_cast<const unsigned char*>(pool + d.a_off);
+        const unsigned char* Xb = reinterpret_cast<const unsigned char*>(
             ((d.src & SRC1) ? x1 : x0) + int64_t(d.src & 0x7fffffff) * RHS_TILE);
         const int K = d.k;
-        const int ksfull = K >> 2;
-        const unsigned step = E * 4u * unsigned(M);   // bytes per full k-step
-        int ks = 0;
-        for (; ks + kUnroll <= ksfull; ks += kUnroll) {
-            T bv[kUnroll];
-            T av[kUnroll][RTW];
+        const int G = K >> 4;
+        int g = 0;
+        for (; g + GU <= G; g += GU) {
+            T bv[GU][4];
+            vec4 av[GU][RTW];
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) bv[u] = ld<T>(Xk + E * 64u * u, xoff);
+            for (int h = 0; h < GU; ++h)
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u) {
-                const unsigned char* Au = Ak + step * u;
+                for (int u = 0; u < 4; ++u) bv[h][u] = ld<T>(Xb + E * (256u * (g + h) + 64u * u), xoff);
 #pragma unroll
-                for (int r = 0; r < RTW; ++r) {
-                    const T v = ld<T>(Au, off[r]);
-                    av[u][r] = ok[r] ? v : T(0);
-                }
-            }
+            for (int h = 0; h < GU; ++h)
 #pragma unroll
-            for (int u = 0; u < kUnroll; ++u)
+                for (int r = 0; r < RTW; ++r) av[h][r] = ld<vec4>(Ab + gstep * (g + h), goff[r]);
 #pragma unroll
-                for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(av[u][r], bv[u], acc[r]);
-            Ak += step * kUnroll;
-            Xk += E * 64u * kUnroll;
+            for (int h = 0; h < GU; ++h)
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[h][r][u] : T(0), bv[h][u], acc[r]);
         }
-        const int ks_end = (K + 3) >> 2;
-        for (; ks < ks_end; ++ks) {
-            const unsigned kv = unsigned(K - 4 * ks < 4 ? K - 4 * ks : 4);
-            const T bl = ld<T>(Xk, kk < kv ? xoff : 0u);
-            const T bv = kk < kv ? bl : T(0);
+        for (; g < G; ++g) {
+            T bv[4];
+            vec4 av[RTW];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) bv[u] = ld<T>(Xb + E * (256u * g + 64u * u), xoff);
+#pragma unroll
+            for (int r = 0; r < RTW; ++r) av[r] = ld<vec4>(Ab + gstep * g, goff[r]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[r][u] : T(0), bv[u], acc[r]);
+        }
+        // tail: K - 16 G columns in k-steps of at most 4
+        const int kt = K - 16 * G;
+        const unsigned char* At = Ab + gstep * G;
+        const unsigned char* Xt = Xb + E * 256u * G;
+        for (int ks = 0; 4 * ks < kt; ++ks) {
+            const unsigned kv = unsigned(kt - 4 * ks < 4 ? kt - 4 * ks : 4);
+            const T bl = ld<T>(Xt, kk < kv ? E * (64u * ks) + xoff : 0u);
+            const T bvt = kk < kv ? bl : T(0);
 #pragma unroll
             for (int r = 0; r < RTW; ++r) {
                 const int rt = rg * RTW + r;
                 const unsigned rv = unsigned(M - 16 * rt < 16 ? M - 16 * rt : 16);
                 const bool valid = rt < RT && i < rv && kk < kv;
-                const T al = ld<T>(Ak, valid ? E * (16u * rt * kv + kk * rv + i) : 0u);
-                acc[r] = Mfma<T>::mma(valid ? al : T(0), bv, acc[r]);
+                const T al = ld<T>(At, valid ? E * (4u * M * ks + 16u * rt * kv + kk * rv + i) : 0u);
+                acc[r] = Mfma<T>::mma(valid ? al : T(0), bvt, acc[r]);
             }
-            Ak += step;
-            Xk += E * 64u;
         }
     }
 }
-
-template <typename IO>
-__device__ inline double io_load(const void* p, int64_t i) { return double(static_cast<const IO*>(p)[i]); }
 
 template <typename T, int RTW, int NRG, int EPI>
 __global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogue epi) {
@@ -189,130 +201,151 @@ __global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogu
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
             if (row >= M) continue;
+            const int64_t o = (int64_t(it.out_row) + row) * RHS_TILE + q;
             if (EPI == EPI_STORE) {
-                static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + q] = acc[r][v];
+                static_cast<T*>(a.y)[o] = acc[r][v];
             } else {
-                if (q >= epi.nr) continue;
                 const int64_t pos = int64_t(it.out_row) + row;
-                const int64_t node = epi.perm[pos];
-                const int64_t base = int64_t(q) * epi.n_nodes;
-                const bool f32 = epi.io == 1;
-                double y = double(acc[r][v]);
-                y += epi.diag[pos] * (f32 ? io_load<float>(epi.u1, base + node) : io_load<double>(epi.u1, base + node));
+                double y = double(acc[r][v]) + epi.diag[pos] * epi.x64[o];
                 if (epi.ns_off != nullptr) {
                     double s = 0.0;
-                    for (int64_t e = epi.ns_off[pos]; e < epi.ns_off[pos + 1]; ++e) {
-                        const int64_t c = epi.ns_col[e];
-                        s += epi.ns_val[e] * (f32 ? io_load<float>(epi.u1, base + c) : io_load<double>(epi.u1, base + c));
-                    }
+                    for (int64_t e = epi.ns_off[pos]; e < epi.ns_off[pos + 1]; ++e)
+                        s += epi.ns_val[e] * epi.x64[int64_t(epi.ns_pos[e]) * RHS_TILE + q];
                     y += s;
                 }
-                if (f32) static_cast<float*>(epi.u2)[base + node] = float(y);
-                else static_cast<double*>(epi.u2)[base + node] = y;
+                epi.y64[o] = y;
             }
         }
     }
 }
 
+// x[p][q] = u1[q][node] for the node at cluster position p = iperm[node];
+// one thread per node: coalesced reads of u1, one contiguous row write.
 template <typename IO, typename T>
 __global__ void __launch_bounds__(256) k_permute(const IO* __restrict__ u1, int64_t n, int nr,
-                                                 const int32_t* __restrict__ perm, T* __restrict__ x) {
-    const int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (g >= n * RHS_TILE) return;
-    const int64_t p = g >> 4;
-    const int q = int(g & 15);
-    x[g] = q < nr ? T(u1[int64_t(q) * n + perm[p]]) : T(0);
+                                                 const int32_t* __restrict__ iperm, T* __restrict__ x,
+                                                 double* __restrict__ x64) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = iperm[i];
+    T v[RHS_TILE];
+    double w[RHS_TILE];
+#pragma unroll
+    for (int q = 0; q < RHS_TILE; ++q) {
+        w[q] = q < nr ? double(u1[int64_t(q) * n + i]) : 0.0;
+        v[q] = T(w[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < RHS_TILE; ++q) x[p * RHS_TILE + q] = v[q];
+    if (x64 != nullptr)
+#pragma unroll
+        for (int q = 0; q < RHS_TILE; ++q) x64[p * RHS_TILE + q] = w[q];
 }
 
-// Mode products of the Kronecker transfer E = Ex (x) Ey (x) Ez on one cluster's
-// k x QC slab (index nu = lx + m ly + m^2 lz, columns innermost).
-//   TRANS: out[l] = sum_l' E[l'][l] in[l']  (E^T, upward)   else  out[l'] = sum_l E[l'][l] in[l]
-template <typename T, bool TRANS>
-__device__ inline void mode_product(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ e, int m,
-                                    int axis, int qc) {
-    const int k = m * m * m;
-    const int stride = axis == 0 ? 1 : (axis == 1 ? m : m * m);
-    for (int idx = threadIdx.x; idx < k * qc; idx += blockDim.x) {
-        const int nu = idx / qc, q = idx % qc;
-        const int l = (nu / stride) % m;
-        const int base = nu - l * stride;
-        T s = 0;
-        for (int p = 0; p < m; ++p) {
-            const T ev = TRANS ? e[p * m + l] : e[l * m + p];
-            s += ev * in[(base + p * stride) * qc + q];
+// u2[q][node] = y64[iperm[node]][q]; one thread per node.
+template <typename IO>
+__global__ void __launch_bounds__(256) k_unpermute(const double* __restrict__ y64, int64_t n, int nr,
+                                                   const int32_t* __restrict__ iperm, IO* __restrict__ u2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t p = iperm[i];
+    double v[RHS_TILE];
+#pragma unroll
+    for (int q = 0; q < RHS_TILE; ++q) v[q] = y64[p * RHS_TILE + q];
+#pragma unroll
+    for (int q = 0; q < RHS_TILE; ++q)
+        if (q < nr) u2[int64_t(q) * n + i] = IO(v[q]);
+}
+
+// One mode product of the Kronecker transfer E = Ex (x) Ey (x) Ez on a k x QC
+// slab in LDS (index nu = lx + m ly + m^2 lz, columns innermost), one thread
+// per line of M values along the axis:
+//   UP: out[l] = sum_l' E[l'][l] in[l']  (E^T)     else  out[l'] = sum_l E[l'][l] in[l]
+template <typename T, int M, int QC, int AXIS, bool UP, bool ADD>
+__device__ inline void mode_product(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ e) {
+    constexpr int STRIDE = AXIS == 0 ? 1 : (AXIS == 1 ? M : M * M);
+    for (int line = threadIdx.x; line < M * M * QC; line += blockDim.x) {
+        const int q = line % QC, rest = line / QC;
+        const int j1 = rest % M, j2 = rest / M;
+        const int base = AXIS == 0 ? M * j1 + M * M * j2 : (AXIS == 1 ? j1 + M * M * j2 : j1 + M * j2);
+        T v[M];
+#pragma unroll
+        for (int p = 0; p < M; ++p) v[p] = in[(base + p * STRIDE) * QC + q];
+#pragma unroll
+        for (int l = 0; l < M; ++l) {
+            T s = 0;
+#pragma unroll
+            for (int p = 0; p < M; ++p) s += (UP ? e[p * M + l] : e[l * M + p]) * v[p];
+            T* o = out + (base + l * STRIDE) * QC + q;
+            *o = ADD ? *o + s : s;
         }
-        out[idx] = s;
     }
 }
 
-template <typename T>
+template <typename T, int M>
+constexpr int transfer_qc() {
+    int qc = RHS_TILE;
+    while (qc > 1 && 3 * M * M * M * qc * int(sizeof(T)) > 48 * 1024) qc >>= 1;
+    return qc;
+}
+
+template <typename T, int M>
 __global__ void __launch_bounds__(256) k_upward(int32_t c_begin, const int32_t* __restrict__ child0,
                                                 const int32_t* __restrict__ child1, const T* __restrict__ efac,
-                                                T* __restrict__ xh, int m, int qc) {
-    extern __shared__ unsigned char smem_raw[];
-    T* s = reinterpret_cast<T*>(smem_raw);
-    const int k = m * m * m;
+                                                T* __restrict__ xh) {
+    constexpr int K = M * M * M, QC = transfer_qc<T, M>(), MM = M * M;
+    __shared__ T e[2][3][MM];
+    __shared__ T b0[K * QC], b1[K * QC], acc[K * QC];
     const int32_t c = c_begin + blockIdx.x;
     const int32_t ch[2] = {child0[c], child1[c]};
     if (ch[0] < 0) return;   // leaf: its xhat comes from the leaf forward
-    T* e = s;                             // 2 children x 3 axes x m x m
-    T* b0 = s + 6 * 64;
-    T* b1 = b0 + k * qc;
-    T* acc = b1 + k * qc;
-    for (int idx = threadIdx.x; idx < 6 * m * m; idx += blockDim.x) {
-        const int which = idx / (3 * m * m);
-        e[which * 3 * 64 + (idx % (3 * m * m)) / (m * m) * 64 + idx % (m * m)] =
-            efac[int64_t(ch[which]) * 3 * m * m + idx % (3 * m * m)];
+    for (int idx = threadIdx.x; idx < 6 * MM; idx += blockDim.x) {
+        const int w = idx / (3 * MM), r = idx % (3 * MM);
+        e[w][r / MM][r % MM] = efac[int64_t(ch[w]) * 3 * MM + r];
     }
-    for (int q0 = 0; q0 < RHS_TILE; q0 += qc) {
-        for (int idx = threadIdx.x; idx < k * qc; idx += blockDim.x) acc[idx] = 0;
+    for (int q0 = 0; q0 < RHS_TILE; q0 += QC) {
+#pragma unroll
         for (int w = 0; w < 2; ++w) {
             __syncthreads();
-            const T* src = xh + int64_t(ch[w]) * k * RHS_TILE;
-            for (int idx = threadIdx.x; idx < k * qc; idx += blockDim.x)
-                b0[idx] = src[(idx / qc) * RHS_TILE + q0 + idx % qc];
+            const T* src = xh + int64_t(ch[w]) * K * RHS_TILE + q0;
+            for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) b0[idx] = src[(idx / QC) * RHS_TILE + idx % QC];
             __syncthreads();
-            mode_product<T, true>(b0, b1, e + w * 3 * 64 + 2 * 64, m, 2, qc);
+            mode_product<T, M, QC, 2, true, false>(b0, b1, e[w][2]);
             __syncthreads();
-            mode_product<T, true>(b1, b0, e + w * 3 * 64 + 1 * 64, m, 1, qc);
+            mode_product<T, M, QC, 1, true, false>(b1, b0, e[w][1]);
             __syncthreads();
-            mode_product<T, true>(b0, b1, e + w * 3 * 64 + 0 * 64, m, 0, qc);
-            __syncthreads();
-            for (int idx = threadIdx.x; idx < k * qc; idx += blockDim.x) acc[idx] += b1[idx];
+            if (w == 0) mode_product<T, M, QC, 0, true, false>(b0, acc, e[w][0]);
+            else mode_product<T, M, QC, 0, true, true>(b0, acc, e[w][0]);
         }
         __syncthreads();
-        T* dst = xh + int64_t(c) * k * RHS_TILE;
-        for (int idx = threadIdx.x; idx < k * qc; idx += blockDim.x) dst[(idx / qc) * RHS_TILE + q0 + idx % qc] = acc[idx];
+        T* dst = xh + int64_t(c) * K * RHS_TILE + q0;
+        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) dst[(idx / QC) * RHS_TILE + idx % QC] = acc[idx];
     }
 }
 
-template <typename T>
+template <typename T, int M>
 __global__ void __launch_bounds__(256) k_downward(int32_t c_begin, const int32_t* __restrict__ parent,
-                                                  const T* __restrict__ efac, T* __restrict__ yh, int m, int qc) {
-    extern __shared__ unsigned char smem_raw[];
-    T* s = reinterpret_cast<T*>(smem_raw);
-    const int k = m * m * m;
+                                                  const T* __restrict__ efac, T* __restrict__ yh) {
+    constexpr int K = M * M * M, QC = transfer_qc<T, M>(), MM = M * M;
+    __shared__ T e[3][MM];
+    __shared__ T b0[K * QC], b1[K * QC];
     const int32_t c = c_begin + blockIdx.x;
     const int32_t p = parent[c];
     if (p < 0) return;
-    T* e = s;
-    T* b0 = s + 3 * 64;
-    T* b1 = b0 + k * qc;
-    for (int idx = threadIdx.x; idx < 3 * m * m; idx += blockDim.x)
-        e[(idx / (m * m)) * 64 + idx % (m * m)] = efac[int64_t(c) * 3 * m * m + idx];
-    for (int q0 = 0; q0 < RHS_TILE; q0 += qc) {
+    for (int idx = threadIdx.x; idx < 3 * MM; idx += blockDim.x) e[idx / MM][idx % MM] = efac[int64_t(c) * 3 * MM + idx];
+    for (int q0 = 0; q0 < RHS_TILE; q0 += QC) {
         __syncthreads();
-        const T* src = yh + int64_t(p) * k * RHS_TILE;
-        for (int idx = threadIdx.x; idx < k * qc; idx += blockDim.x) b0[idx] = src[(idx / qc) * RHS_TILE + q0 + idx % qc];
+        const T* src = yh + int64_t(p) * K * RHS_TILE + q0;
+        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) b0[idx] = src[(idx / QC) * RHS_TILE + idx % QC];
         __syncthreads();
-        mode_product<T, false>(b0, b1, e + 2 * 64, m, 2, qc);
+        mode_product<T, M, QC, 2, false, false>(b0, b1, e[2]);
         __syncthreads();
-        mode_product<T, false>(b1, b0, e + 1 * 64, m, 1, qc);
+        mode_product<T, M, QC, 1, false, false>(b1, b0, e[1]);
         __syncthreads();
-        mode_product<T, false>(b0, b1, e + 0 * 64, m, 0, qc);
+        mode_product<T, M, QC, 0, false, false>(b0, b1, e[0]);
         __syncthreads();
-        T* dst = yh + int64_t(c) * k * RHS_TILE;
-        for (int idx = threadIdx.x; idx < k * qc; idx += blockDim.x) dst[(idx / qc) * RHS_TILE + q0 + idx % qc] += b1[idx];
+        T* dst = yh + int64_t(c) * K * RHS_TILE + q0;
+        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) dst[(idx / QC) * RHS_TILE + idx % QC] += b1[idx];
     }
 }
 
@@ -342,28 +375,62 @@ hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nr
     return hipErrorInvalidValue;
 }
 
-inline int transfer_qc(int k, size_t elem, int buffers) {
-    int qc = RHS_TILE;
-    while (qc > 1 && size_t(buffers) * k * qc * elem > 48 * 1024) qc >>= 1;
-    return qc;
+template <typename T>
+hipError_t upward_m(int m, unsigned grid, hipStream_t st, int32_t c_begin, const int32_t* child0,
+                    const int32_t* child1, const T* e, T* xh) {
+    switch (m) {
+#define H2DLP_M(MM_) case MM_: hipLaunchKernelGGL((k_upward<T, MM_>), dim3(grid), dim3(256), 0, st, c_begin, child0, child1, e, xh); break;
+        H2DLP_M(1) H2DLP_M(2) H2DLP_M(3) H2DLP_M(4) H2DLP_M(5) H2DLP_M(6) H2DLP_M(7) H2DLP_M(8)
+#undef H2DLP_M
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t downward_m(int m, unsigned grid, hipStream_t st, int32_t c_begin, const int32_t* parent, const T* e,
+                      T* yh) {
+    switch (m) {
+#define H2DLP_M(MM_) case MM_: hipLaunchKernelGGL((k_downward<T, MM_>), dim3(grid), dim3(256), 0, st, c_begin, parent, e, yh); break;
+        H2DLP_M(1) H2DLP_M(2) H2DLP_M(3) H2DLP_M(4) H2DLP_M(5) H2DLP_M(6) H2DLP_M(7) H2DLP_M(8)
+#undef H2DLP_M
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_permute(const void* u1, int io, int64_t n_nodes, int nr, const int32_t* perm, void* x, int prec,
-                          hipStream_t st) {
-    const unsigned grid = unsigned((n_nodes * RHS_TILE + 255) / 256);
+hipError_t launch_permute(const void* u1, int io, int64_t n_nodes, int nr, const int32_t* iperm, void* x,
+                          double* x64, int prec, hipStream_t st) {
+    const unsigned grid = unsigned((n_nodes + 255) / 256);
     if (io == 1) {
         if (prec == P_FP64)
-            hipLaunchKernelGGL((k_permute<float, double>), dim3(grid), dim3(256), 0, st, static_cast<const float*>(u1), n_nodes, nr, perm, static_cast<double*>(x));
+            hipLaunchKernelGGL((k_permute<float, double>), dim3(grid), dim3(256), 0, st, static_cast<const float*>(u1),
+                               n_nodes, nr, iperm, static_cast<double*>(x), nullptr);
         else
-            hipLaunchKernelGGL((k_permute<float, float>), dim3(grid), dim3(256), 0, st, static_cast<const float*>(u1), n_nodes, nr, perm, static_cast<float*>(x));
+            hipLaunchKernelGGL((k_permute<float, float>), dim3(grid), dim3(256), 0, st, static_cast<const float*>(u1),
+                               n_nodes, nr, iperm, static_cast<float*>(x), x64);
     } else {
         if (prec == P_FP64)
-            hipLaunchKernelGGL((k_permute<double, double>), dim3(grid), dim3(256), 0, st, static_cast<const double*>(u1), n_nodes, nr, perm, static_cast<double*>(x));
+            hipLaunchKernelGGL((k_permute<double, double>), dim3(grid), dim3(256), 0, st, static_cast<const double*>(u1),
+                               n_nodes, nr, iperm, static_cast<double*>(x), nullptr);
         else
-            hipLaunchKernelGGL((k_permute<double, float>), dim3(grid), dim3(256), 0, st, static_cast<const double*>(u1), n_nodes, nr, perm, static_cast<float*>(x));
+            hipLaunchKernelGGL((k_permute<double, float>), dim3(grid), dim3(256), 0, st, static_cast<const double*>(u1),
+                               n_nodes, nr, iperm, static_cast<float*>(x), x64);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute(const double* y64, int io, int64_t n_nodes, int nr, const int32_t* iperm, void* u2,
+                            hipStream_t st) {
+    const unsigned grid = unsigned((n_nodes + 255) / 256);
+    if (io == 1)
+        hipLaunchKernelGGL((k_unpermute<float>), dim3(grid), dim3(256), 0, st, y64, n_nodes, nr, iperm,
+                           static_cast<float*>(u2));
+    else
+        hipLaunchKernelGGL((k_unpermute<double>), dim3(grid), dim3(256), 0, st, y64, n_nodes, nr, iperm,
+                           static_cast<double*>(u2));
     return hipGetLastError();
 }
 
@@ -393,37 +460,19 @@ hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int 
 hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, const int32_t* child1, const void* e,
                          void* xh, int m, int prec, hipStream_t st) {
     if (c_end <= c_begin) return hipSuccess;
-    const int k = m * m * m;
-    if (prec == P_FP64) {
-        const int qc = transfer_qc(k, sizeof(double), 3);
-        const size_t lds = (6 * 64 + 3 * size_t(k) * qc) * sizeof(double);
-        hipLaunchKernelGGL(k_upward<double>, dim3(unsigned(c_end - c_begin)), dim3(256), lds, st, c_begin, child0,
-                           child1, static_cast<const double*>(e), static_cast<double*>(xh), m, qc);
-    } else {
-        const int qc = transfer_qc(k, sizeof(float), 3);
-        const size_t lds = (6 * 64 + 3 * size_t(k) * qc) * sizeof(float);
-        hipLaunchKernelGGL(k_upward<float>, dim3(unsigned(c_end - c_begin)), dim3(256), lds, st, c_begin, child0,
-                           child1, static_cast<const float*>(e), static_cast<float*>(xh), m, qc);
-    }
-    return hipGetLastError();
+    const unsigned grid = unsigned(c_end - c_begin);
+    if (prec == P_FP64)
+        return upward_m<double>(m, grid, st, c_begin, child0, child1, static_cast<const double*>(e), static_cast<double*>(xh));
+    return upward_m<float>(m, grid, st, c_begin, child0, child1, static_cast<const float*>(e), static_cast<float*>(xh));
 }
 
 hipError_t launch_downward(int32_t c_begin, int32_t c_end, const int32_t* parent, const void* e, void* yh, int m,
                            int prec, hipStream_t st) {
     if (c_end <= c_begin) return hipSuccess;
-    const int k = m * m * m;
-    if (prec == P_FP64) {
-        const int qc = transfer_qc(k, sizeof(double), 2);
-        const size_t lds = (3 * 64 + 2 * size_t(k) * qc) * sizeof(double);
-        hipLaunchKernelGGL(k_downward<double>, dim3(unsigned(c_end - c_begin)), dim3(256), lds, st, c_begin, parent,
-                           static_cast<const double*>(e), static_cast<double*>(yh), m, qc);
-    } else {
-        const int qc = transfer_qc(k, sizeof(float), 2);
-        const size_t lds = (3 * 64 + 2 * size_t(k) * qc) * sizeof(float);
-        hipLaunchKernelGGL(k_downward<float>, dim3(unsigned(c_end - c_begin)), dim3(256), lds, st, c_begin, parent,
-                           static_cast<const float*>(e), static_cast<float*>(yh), m, qc);
-    }
-    return hipGetLastError();
+    const unsigned grid = unsigned(c_end - c_begin);
+    if (prec == P_FP64)
+        return downward_m<double>(m, grid, st, c_begin, parent, static_cast<const double*>(e), static_cast<double*>(yh));
+    return downward_m<float>(m, grid, st, c_begin, parent, static_cast<const float*>(e), static_cast<float*>(yh));
 }
 
 }  // namespace h2dlp

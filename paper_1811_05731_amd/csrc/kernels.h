@@ -56,16 +56,12 @@ hipError_t launch_build_near(DevMesh mesh, const NearDesc* near, int64_t n_near,
 
 // ---------------------------------------------------------------- apply
 
-struct LeafEpilogue {           // u2 = y + D x (+ near-singular FP64 part), scattered to node order
-    const int32_t* perm;
+struct LeafEpilogue {           // y64 = y + D x64 (+ near-singular FP64 part), cluster order
     const double* diag;         // by cluster position
-    const void* u1;             // (nrhs, N) of io type, already offset to this pass
-    void* u2;
-    int64_t n_nodes;
-    int32_t nr;                 // valid columns in this pass (<= 16)
-    int32_t io;                 // 0 FP64, 1 FP32
+    const double* x64;          // FP64 input rows (cluster order, 16 columns)
+    double* y64;                // FP64 output rows (cluster order, 16 columns)
     const int64_t* ns_off;      // by cluster position; NULL when there is no FP64 subset
-    const int32_t* ns_col;      // node index
+    const int32_t* ns_pos;      // column as a cluster position
     const double* ns_val;
 };
 
@@ -80,8 +76,10 @@ struct ProductArgs {
     void* y;
 };
 
-hipError_t launch_permute(const void* u1, int io, int64_t n_nodes, int nr, const int32_t* perm, void* x, int prec,
-                          hipStream_t st);
+hipError_t launch_permute(const void* u1, int io, int64_t n_nodes, int nr, const int32_t* iperm, void* x,
+                          double* x64, int prec, hipStream_t st);
+hipError_t launch_unpermute(const double* y64, int io, int64_t n_nodes, int nr, const int32_t* iperm, void* u2,
+                            hipStream_t st);
 // prefer_rows: split the rows of one item over the 4 waves (else split its blocks)
 hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st);
 hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st);

@@ -4,13 +4,19 @@
 // Every dense block the apply multiplies -- a leaf's transposed column basis
 // W_s^T (k x n_s), a coupling matrix S_ts (k x k), a leaf's row basis V_t
 // (n_t x k) and a near-field block K|_{t x s} (n_t x n_s) -- is stored in the
-// order in which a wave64 feeds it to the 16x16x4 MFMA as the A operand, with
-// no padding: the M x K block is cut into 16 x 4 chunks (row tile rt, k-step
-// ks), chunks ordered ks-major, and inside a chunk of rv x kv valid entries the
-// entry (row 16 rt + i, col 4 ks + kk) sits at kk * rv + i.  Lane l of the wave
-// reads the entry with i = l % 16, kk = l / 16, so every chunk is one
-// contiguous run of at most 64 elements.  Only the last row tile and the last
-// k-step can be partial.
+// order in which a wave64 feeds it to the 16x16x4 MFMA as the A operand (lane
+// l holds row l % 16, column l / 16 of a 16 x 4 tile), with no padding:
+//
+//  * columns come in G = K / 16 full groups of 16 and a tail of K - 16 G;
+//  * group g, row tile rt (rv = min(16, M - 16 rt) valid rows) is one
+//    contiguous chunk of 16 rv entries at 16 M g + 256 rt; entry
+//    (16 rt + i, 16 g + 4 u + kk) sits at (kk rv + i) 4 + u, so a lane reads
+//    the four k-steps u of its (i, kk) with one 4-element load;
+//  * the tail follows at 16 M G, cut into k-steps of kv <= 4 columns; chunk
+//    (ks, rt) of rv kv entries at 4 M ks + 16 rt kv, entry at kk rv + i.
+//
+// Only the last row tile and the last tail k-step can be partial.  Blocks
+// start on 16-element boundaries (BLOCK_ALIGN) so the 4-element loads align.
 #pragma once
 
 #include <cstdint>
@@ -27,11 +33,21 @@ namespace h2dlp {
 
 constexpr int RHS_TILE = 16;   // right-hand sides per pass (the MFMA N dimension)
 
+constexpr int64_t BLOCK_ALIGN = 16;
+
+H2DLP_HD inline int64_t align_block(int64_t off) { return (off + BLOCK_ALIGN - 1) / BLOCK_ALIGN * BLOCK_ALIGN; }
+
 H2DLP_HD inline int64_t a_offset(int M, int K, int row, int col) {
-    const int rt = row >> 4, i = row & 15, ks = col >> 2, kk = col & 3;
+    const int rt = row >> 4, i = row & 15;
     const int rv = (M - 16 * rt) < 16 ? (M - 16 * rt) : 16;
-    const int kv = (K - 4 * ks) < 4 ? (K - 4 * ks) : 4;
-    return int64_t(4) * M * ks + int64_t(16) * rt * kv + kk * rv + i;
+    const int G = K >> 4;
+    if (col < 16 * G) {
+        const int g = col >> 4, u = (col & 15) >> 2, kk = col & 3;
+        return int64_t(16) * M * g + 256 * rt + (kk * rv + i) * 4 + u;
+    }
+    const int c = col - 16 * G, ks = c >> 2, kk = c & 3, kt = K - 16 * G;
+    const int kv = (kt - 4 * ks) < 4 ? (kt - 4 * ks) : 4;
+    return int64_t(16) * M * G + int64_t(4) * M * ks + 16 * rt * kv + kk * rv + i;
 }
 
 // One output tile of a grouped block product: rows [out_row, out_row + m) of
