@@ -130,6 +130,7 @@ struct h2dlp_ctx {
     size_t ws_bytes = 0, ws_x = 0, ws_x64 = 0, ws_y64 = 0, ws_xh = 0;
     int32_t n_items_fwd = 0, n_items_cpl = 0, n_items_leaf = 0;
     int32_t rt_leaf = 1;
+    int kp = 0;                      // stored columns of a coupling block
     bool materialized = false;
     // host-side plan
     std::vector<int32_t> child0, child1, parent;
@@ -255,6 +256,8 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     for (size_t b = 0; b < S.far.size(); ++b)
         far_by_t[h->gid_of_pre[S.far[b].first]].push_back(h->gid_of_pre[S.far[b].second]);
     int64_t off_s = 0;
+    const int kp = coupling_cols(k);
+    h->kp = kp;
     for (int32_t g = 0; g < C; ++g) {
         auto& lst = far_by_t[g];
         std::sort(lst.begin(), lst.end());
@@ -262,8 +265,8 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         for (int32_t s : lst) {
             off_s = align_block(off_s);
             h->fars.push_back(FarDesc{g, s, off_s});
-            h->blks_cpl.push_back(BlkDesc{off_s, k, s * k});
-            off_s += int64_t(k) * k;
+            h->blks_cpl.push_back(BlkDesc{off_s, kp, s * k});
+            off_s += int64_t(k) * kp;
         }
     }
     // leaf output: V_t (n_t x k) then the near blocks of t (sorted by source position)
@@ -398,7 +401,8 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf, stream),
           "row basis");
     check(launch_build_transfer(d_boxes, h->d_parent, C, m, h->prec, h->d_e, stream), "transfer");
-    check(launch_build_coupling(d_boxes, m, d_far, int64_t(h->fars.size()), h->prec, h->d_pool_s, stream), "coupling");
+    check(launch_build_coupling(d_boxes, m, h->kp, d_far, int64_t(h->fars.size()), h->prec, h->d_pool_s, stream),
+          "coupling");
     check(launch_build_near(dm, d_near, int64_t(h->nears.size()), h->prec, h->d_pool_leaf,
                             fp64 ? nullptr : h->d_ns_off, fp64 ? nullptr : h->d_ns_pos, fp64 ? nullptr : h->d_ns_val,
                             stream),
@@ -463,7 +467,7 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
 
         ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
         rec_begin(h, s, &ev);
-        check(launch_product_store(cpl, prec, false, s), "coupling");
+        check(launch_coupling(cpl, k, prec, s), "coupling");
         rec_end(h, s, 3, ev);
 
         for (int l = 1; l <= h->S.depth; ++l) {

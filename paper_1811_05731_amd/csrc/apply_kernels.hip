@@ -70,86 +70,108 @@ __device__ inline V ld(const unsigned char* base, unsigned byte_off) {
 }
 
 // Accumulate sum_b A_b X_b of one item into acc[RTW] (row tiles rg*RTW ...).
-// Each lane keeps, per row tile, the byte offset of its 4-entry vector inside
-// a 16-column group chunk; lanes outside a partial tile read the chunk start
-// and discard it; tiles past the item's rows multiply zeros (branch-free).
+//
+// A wave walks its blocks (every nbg-th of the item) as a flat sequence of
+// units -- each 16-column group of a block, then one unit for the block's tail
+// of K - 16 G columns (up to 4 k-steps loaded together) -- with the next unit's
+// loads in flight while the current unit's MFMAs run.  A unit is RTW vectors of
+// 4 A entries (one per k-step u) and 4 B entries.  Each lane keeps, per row
+// tile, the byte offset of its group vector; lanes outside a partial tile read
+// the chunk start and discard it; tiles past the item's rows multiply zeros.
 template <typename T, int RTW>
 __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict__ blks, const T* __restrict__ pool,
                                   const T* __restrict__ x0, const T* __restrict__ x1, int rg, int bg, int nbg,
                                   typename Mfma<T>::acc* acc) {
     typedef typename Mfma<T>::vec4 vec4;
-    constexpr int GU = Mfma<T>::kGroupUnroll;
     constexpr unsigned E = sizeof(T);
     const unsigned lane = threadIdx.x & 63;
     const unsigned i = lane & 15, kk = lane >> 4;
     const int M = it.m;
     const int RT = (M + 15) >> 4;
-    unsigned goff[RTW];
+    unsigned goff[RTW], rvs[RTW];
     bool ok[RTW];
 #pragma unroll
     for (int r = 0; r < RTW; ++r) {
         const int rt = rg * RTW + r;
-        const unsigned rv = unsigned(M - 16 * rt < 16 ? M - 16 * rt : 16);
-        ok[r] = rt < RT && i < rv;
-        goff[r] = ok[r] ? E * (256u * rt + 4u * (kk * rv + i)) : 0u;
+        rvs[r] = unsigned(M - 16 * rt < 16 ? M - 16 * rt : 16);
+        ok[r] = rt < RT && i < rvs[r];
+        goff[r] = ok[r] ? E * (256u * rt + 4u * (kk * rvs[r] + i)) : 0u;
     }
     const unsigned xoff = E * lane;
-    const unsigned gstep = E * 16u * unsigned(M);   // bytes of one 16-column group
-    for (int b = it.blk_begin + bg; b < it.blk_end; b += nbg) {
-        const BlkDesc d = blks[b];
-        const unsigned char* Ab = reinterpret_cast<const unsigned char*>(pool + d.a_off);
+    const unsigned gstep = E * 16u * unsigned(M);
+    const unsigned char* P = reinterpret_cast<const unsigned char*>(pool);
+
+    auto load_unit = [&](const BlkDesc& d, int g, vec4* av, T* bv) {
+        const unsigned char* Ab = P + int64_t(d.a_off) * E;
         const unsigned char* Xb = reinterpret_cast<const unsigned char*>(
             ((d.src & SRC1) ? x1 : x0) + int64_t(d.src & 0x7fffffff) * RHS_TILE);
-        const int K = d.k;
-        const int G = K >> 4;
-        int g = 0;
-        for (; g + GU <= G; g += GU) {
-            T bv[GU][4];
-            vec4 av[GU][RTW];
-#pragma unroll
-            for (int h = 0; h < GU; ++h)
-#pragma unroll
-                for (int u = 0; u < 4; ++u) bv[h][u] = ld<T>(Xb + E * (256u * (g + h) + 64u * u), xoff);
-#pragma unroll
-            for (int h = 0; h < GU; ++h)
-#pragma unroll
-                for (int r = 0; r < RTW; ++r) av[h][r] = ld<vec4>(Ab + gstep * (g + h), goff[r]);
-#pragma unroll
-            for (int h = 0; h < GU; ++h)
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[h][r][u] : T(0), bv[h][u], acc[r]);
-        }
-        for (; g < G; ++g) {
-            T bv[4];
-            vec4 av[RTW];
+        const int G = d.k >> 4;
+        if (g < G) {
 #pragma unroll
             for (int u = 0; u < 4; ++u) bv[u] = ld<T>(Xb + E * (256u * g + 64u * u), xoff);
 #pragma unroll
             for (int r = 0; r < RTW; ++r) av[r] = ld<vec4>(Ab + gstep * g, goff[r]);
+        } else {
+            const int kt = d.k - 16 * G;
+            const unsigned char* At = Ab + gstep * G;
+            const unsigned char* Xt = Xb + E * 256u * G;
 #pragma unroll
-            for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) {
+                const int kvi = kt - 4 * u;
+                const unsigned kv = unsigned(kvi < 0 ? 0 : (kvi < 4 ? kvi : 4));
+                const T bl = ld<T>(Xt, kk < kv ? E * 64u * u + xoff : 0u);
+                bv[u] = kk < kv ? bl : T(0);
 #pragma unroll
-                for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[r][u] : T(0), bv[u], acc[r]);
-        }
-        // tail: K - 16 G columns in k-steps of at most 4
-        const int kt = K - 16 * G;
-        const unsigned char* At = Ab + gstep * G;
-        const unsigned char* Xt = Xb + E * 256u * G;
-        for (int ks = 0; 4 * ks < kt; ++ks) {
-            const unsigned kv = unsigned(kt - 4 * ks < 4 ? kt - 4 * ks : 4);
-            const T bl = ld<T>(Xt, kk < kv ? E * (64u * ks) + xoff : 0u);
-            const T bvt = kk < kv ? bl : T(0);
-#pragma unroll
-            for (int r = 0; r < RTW; ++r) {
-                const int rt = rg * RTW + r;
-                const unsigned rv = unsigned(M - 16 * rt < 16 ? M - 16 * rt : 16);
-                const bool valid = rt < RT && i < rv && kk < kv;
-                const T al = ld<T>(At, valid ? E * (4u * M * ks + 16u * rt * kv + kk * rv + i) : 0u);
-                acc[r] = Mfma<T>::mma(valid ? al : T(0), bvt, acc[r]);
+                for (int r = 0; r < RTW; ++r) {
+                    const unsigned rt = unsigned(rg * RTW + r);
+                    const bool valid = ok[r] && kk < kv;
+                    const T al = ld<T>(At, valid ? E * (4u * M * u + 16u * rt * kv + kk * rvs[r] + i) : 0u);
+                    av[r][u] = valid ? al : T(0);
+                }
             }
         }
+    };
+    auto compute = [&](const vec4* av, const T* bv) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[r][u] : T(0), bv[u], acc[r]);
+    };
+
+    int b = it.blk_begin + bg;
+    if (b >= it.blk_end) return;
+    BlkDesc d = blks[b];
+    int units = (d.k >> 4) + ((d.k & 15) != 0);
+    int g = 0;
+    auto advance = [&]() {
+        if (++g == units) {
+            g = 0;
+            b += nbg;
+            if (b < it.blk_end) {
+                d = blks[b];
+                units = (d.k >> 4) + ((d.k & 15) != 0);
+            }
+        }
+    };
+    vec4 a0[RTW], a1[RTW];
+    T b0[4], b1[4];
+    load_unit(d, g, a0, b0);
+    advance();
+    while (true) {
+        const bool more1 = b < it.blk_end;
+        if (more1) {
+            load_unit(d, g, a1, b1);
+            advance();
+        }
+        compute(a0, b0);
+        if (!more1) break;
+        const bool more0 = b < it.blk_end;
+        if (more0) {
+            load_unit(d, g, a0, b0);
+            advance();
+        }
+        compute(a1, b1);
+        if (!more0) break;
     }
 }
 
@@ -183,40 +205,160 @@ __global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogu
                 for (int v = 0; v < 4; ++v) slot[(r * 4 + v) * 64 + lane] = acc[r][v];
         }
         __syncthreads();
-        if (bg > 0) return;
-        for (int g = 1; g < NBG; ++g) {
-            const T* slot = red + ((g - 1) * NRG + rg) * RTW * 256;
+        if (bg == 0)
+            for (int g = 1; g < NBG; ++g) {
+                const T* slot = red + ((g - 1) * NRG + rg) * RTW * 256;
 #pragma unroll
-            for (int r = 0; r < RTW; ++r)
+                for (int r = 0; r < RTW; ++r)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) acc[r][v] += slot[(r * 4 + v) * 64 + lane];
-        }
+                    for (int v = 0; v < 4; ++v) acc[r][v] += slot[(r * 4 + v) * 64 + lane];
+            }
+        if (EPI == EPI_STORE && bg > 0) return;
     }
 
     const int M = it.m;
     const int q = lane & 15;
+    if (EPI == EPI_STORE) {
 #pragma unroll
-    for (int r = 0; r < RTW; ++r) {
+        for (int r = 0; r < RTW; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
+                if (row < M) static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + q] = acc[r][v];
+            }
+        return;
+    }
+    // leaf output: stage the item's rows in LDS, then every thread finishes
+    // some (row, column) pairs in FP64: y + D x64 + near-singular part
+    T* stage = red + (NBG - 1) * NRG * RTW * 256;
+    if (bg == 0) {
+#pragma unroll
+        for (int r = 0; r < RTW; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
+                if (row < M) stage[row * RHS_TILE + q] = acc[r][v];
+            }
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < M * RHS_TILE; idx += kThreads) {
+        const int row = idx >> 4, col = idx & 15;
+        const int64_t pos = int64_t(it.out_row) + row;
+        const int64_t o = pos * RHS_TILE + col;
+        double y = double(stage[idx]) + epi.diag[pos] * epi.x64[o];
+        if (epi.ns_off != nullptr) {
+            const int64_t e0 = epi.ns_off[pos], e1 = epi.ns_off[pos + 1];
+            double s0 = 0.0, s1 = 0.0;
+            int64_t e = e0;
+            for (; e + 2 <= e1; e += 2) {
+                const int32_t p0 = epi.ns_pos[e], p1 = epi.ns_pos[e + 1];
+                s0 += epi.ns_val[e] * epi.x64[int64_t(p0) * RHS_TILE + col];
+                s1 += epi.ns_val[e + 1] * epi.x64[int64_t(p1) * RHS_TILE + col];
+            }
+            if (e < e1) s0 += epi.ns_val[e] * epi.x64[int64_t(epi.ns_pos[e]) * RHS_TILE + col];
+            y += s0 + s1;
+        }
+        epi.y64[o] = y;
+    }
+}
+
+// Coupling products yhat_t = sum_s S_ts xhat_s for orders with k <= 128.  Every
+// S_ts is stored k x kp, kp = 16 RT (columns k..kp-1 zero), so a block is RT
+// uniform 16-column groups.  A wave takes every 4th block of its item and walks
+// the flattened (block, group) sequence with the next group's loads in flight
+// while the current group's MFMAs run; B rows >= k are read as zero.
+template <typename T, int RT>
+__global__ void __launch_bounds__(kThreads) k_coupling(ProductArgs a, int kvalid) {
+    typedef typename Mfma<T>::acc acc_t;
+    typedef typename Mfma<T>::vec4 vec4;
+    constexpr unsigned E = sizeof(T);
+    constexpr int G = RT;
+    extern __shared__ unsigned char smem_raw[];
+    T* red = reinterpret_cast<T*>(smem_raw);
+
+    const int item = xcd_item(a.n_items);
+    if (item < 0) return;
+    const ItemDesc it = a.items[item];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned lane = threadIdx.x & 63;
+    const unsigned i = lane & 15, kk = lane >> 4;
+    const int M = it.m;
+    unsigned goff[RT];
+    bool ok[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+        const unsigned rv = unsigned(M - 16 * r < 16 ? M - 16 * r : 16);
+        ok[r] = i < rv;
+        goff[r] = ok[r] ? E * (256u * r + 4u * (kk * rv + i)) : 0u;
+    }
+    const unsigned gstep = E * 16u * unsigned(M);
+    const unsigned char* pool = static_cast<const unsigned char*>(a.pool);
+    const unsigned char* xh = static_cast<const unsigned char*>(a.x0);
+    const int first = it.blk_begin + w;
+    const int nb = first < it.blk_end ? (it.blk_end - first + kWaves - 1) / kWaves : 0;
+    const int units = nb * G;
+
+    acc_t acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = acc_t{0, 0, 0, 0};
+    vec4 a0[RT], a1[RT];
+    T b0[4], b1[4];
+
+    auto load = [&](int n, vec4* av, T* bv) {
+        const int j = n / G, g = n - j * G;
+        const BlkDesc d = a.blks[first + kWaves * j];
+        const unsigned char* Ab = pool + int64_t(d.a_off) * E + gstep * g;
+        const unsigned char* Xb = xh + (int64_t(d.src) * RHS_TILE + 256 * g) * E;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const bool in = 16 * g + 4 * u + int(kk) < kvalid;
+            const T v = ld<T>(Xb, in ? E * (64u * u + lane) : 0u);
+            bv[u] = in ? v : T(0);
+        }
+#pragma unroll
+        for (int r = 0; r < RT; ++r) av[r] = ld<vec4>(Ab, goff[r]);
+    };
+    auto compute = [&](const vec4* av, const T* bv) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[r][u] : T(0), bv[u], acc[r]);
+    };
+    int n = 0;
+    if (units > 0) load(0, a0, b0);
+    for (; n + 2 <= units; n += 2) {
+        load(n + 1, a1, b1);
+        compute(a0, b0);
+        if (n + 2 < units) load(n + 2, a0, b0);
+        compute(a1, b1);
+    }
+    if (n < units) compute(a0, b0);
+
+    // fixed-order reduction of the 4 waves, then store rows < M
+    if (w > 0) {
+        T* slot = red + (w - 1) * RT * 256;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) slot[(r * 4 + v) * 64 + lane] = acc[r][v];
+    }
+    __syncthreads();
+    if (w > 0) return;
+    for (int g = 1; g < kWaves; ++g) {
+        const T* slot = red + (g - 1) * RT * 256;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[r][v] += slot[(r * 4 + v) * 64 + lane];
+    }
+    const int q = lane & 15;
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
-            if (row >= M) continue;
-            const int64_t o = (int64_t(it.out_row) + row) * RHS_TILE + q;
-            if (EPI == EPI_STORE) {
-                static_cast<T*>(a.y)[o] = acc[r][v];
-            } else {
-                const int64_t pos = int64_t(it.out_row) + row;
-                double y = double(acc[r][v]) + epi.diag[pos] * epi.x64[o];
-                if (epi.ns_off != nullptr) {
-                    double s = 0.0;
-                    for (int64_t e = epi.ns_off[pos]; e < epi.ns_off[pos + 1]; ++e)
-                        s += epi.ns_val[e] * epi.x64[int64_t(epi.ns_pos[e]) * RHS_TILE + q];
-                    y += s;
-                }
-                epi.y64[o] = y;
-            }
+            const int row = 16 * r + Mfma<T>::row(lane >> 4, v);
+            if (row < M) static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + q] = acc[r][v];
         }
-    }
 }
 
 // x[p][q] = u1[q][node] for the node at cluster position p = iperm[node];
@@ -360,7 +502,8 @@ hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nr
     const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
     if (grid == 0) return hipSuccess;
     const int nbg = kWaves / nrg;
-    const size_t lds = size_t(nbg - 1) * nrg * rtw * 256 * sizeof(T);
+    size_t lds = size_t(nbg - 1) * nrg * rtw * 256 * sizeof(T);
+    if (EPI == EPI_LEAF) lds += size_t(16 * rtw) * RHS_TILE * sizeof(T);   // staged output rows
 #define H2DLP_CASE(RTW_, NRG_)                                                                       \
     if (rtw == RTW_ && nrg == NRG_) {                                                                \
         hipLaunchKernelGGL((k_product<T, RTW_, NRG_, EPI>), dim3(grid), dim3(kThreads), lds, st, a, e); \
@@ -448,6 +591,29 @@ hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows
     LeafEpilogue none{};
     if (prec == P_FP64) return dispatch<double, EPI_STORE>(a, none, rtw, nrg, st);
     return dispatch<float, EPI_STORE>(a, none, rtw, nrg, st);
+}
+
+hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st) {
+    const int rt = (k + 15) / 16;
+    if (rt > 8 || (rt & (rt - 1)) != 0) {   // large orders: generic product (blocks stored k x k)
+        if (rt <= 8) return hipErrorInvalidValue;
+        return launch_product_store(a, prec, false, st);
+    }
+    const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
+    if (grid == 0) return hipSuccess;
+    const size_t lds = size_t(kWaves - 1) * rt * 256 * (prec == P_FP64 ? 8 : 4);
+#define H2DLP_CPL(T_, RT_)                                                                              \
+    if (rt == RT_) {                                                                                    \
+        hipLaunchKernelGGL((k_coupling<T_, RT_>), dim3(grid), dim3(kThreads), lds, st, a, k);           \
+        return hipGetLastError();                                                                       \
+    }
+    if (prec == P_FP64) {
+        H2DLP_CPL(double, 1) H2DLP_CPL(double, 2) H2DLP_CPL(double, 4) H2DLP_CPL(double, 8)
+    } else {
+        H2DLP_CPL(float, 1) H2DLP_CPL(float, 2) H2DLP_CPL(float, 4) H2DLP_CPL(float, 8)
+    }
+#undef H2DLP_CPL
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st) {

@@ -237,23 +237,27 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_transfer(const double* 
     put_prec(e, g, v, prec);
 }
 
-// Coupling matrix of an admissible block: S(nu, mu) = 1/(4 pi |eta^t_nu - eta^s_mu|).
+// Coupling matrix of an admissible block: S(nu, mu) = 1/(4 pi |eta^t_nu - eta^s_mu|),
+// stored k x kp with zero columns mu >= k.
 // BF16X3 stores each entry as (hi, lo) bfloat16, hi = bf16(S), lo = bf16(S - hi).
-__global__ void __launch_bounds__(kBuildThreads) k_build_coupling(const double* boxes, int m, const FarDesc* far,
-                                                                  int prec, void* pool) {
+__global__ void __launch_bounds__(kBuildThreads) k_build_coupling(const double* boxes, int m, int kp,
+                                                                  const FarDesc* far, int prec, void* pool) {
     __shared__ double pt[3][8], ps[3][8];
     const FarDesc F = far[blockIdx.x];
     if (threadIdx.x < 3) cheb_axis(boxes + 6 * int64_t(F.t), threadIdx.x, m, pt[threadIdx.x]);
     else if (threadIdx.x < 6) cheb_axis(boxes + 6 * int64_t(F.s), threadIdx.x - 3, m, ps[threadIdx.x - 3]);
     __syncthreads();
     const int k = m * m * m;
-    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
-        const int nu = e / k, mu = e % k;
-        const double dx = pt[0][nu % m] - ps[0][mu % m];
-        const double dy = pt[1][(nu / m) % m] - ps[1][(mu / m) % m];
-        const double dz = pt[2][nu / (m * m)] - ps[2][mu / (m * m)];
-        const double v = 1.0 / (4.0 * kPi * sqrt(dx * dx + dy * dy + dz * dz));
-        const int64_t off = F.a_off + a_offset(k, k, nu, mu);
+    for (int e = threadIdx.x; e < k * kp; e += blockDim.x) {
+        const int nu = e / kp, mu = e % kp;
+        double v = 0.0;
+        if (mu < k) {
+            const double dx = pt[0][nu % m] - ps[0][mu % m];
+            const double dy = pt[1][(nu / m) % m] - ps[1][(mu / m) % m];
+            const double dz = pt[2][nu / (m * m)] - ps[2][mu / (m * m)];
+            v = 1.0 / (4.0 * kPi * sqrt(dx * dx + dy * dy + dz * dz));
+        }
+        const int64_t off = F.a_off + a_offset(k, kp, nu, mu);
         if (prec == P_BF16X3) {
             const float f = float(v);
             const __hip_bfloat16 hi = __float2bfloat16(f);
@@ -347,10 +351,11 @@ hipError_t launch_build_transfer(const double* boxes, const int32_t* parent, int
     return hipGetLastError();
 }
 
-hipError_t launch_build_coupling(const double* boxes, int m, const FarDesc* far, int64_t n_far, int prec, void* pool,
-                                 hipStream_t st) {
+hipError_t launch_build_coupling(const double* boxes, int m, int kp, const FarDesc* far, int64_t n_far, int prec,
+                                 void* pool, hipStream_t st) {
     if (n_far == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_coupling, dim3(unsigned(n_far)), dim3(kBuildThreads), 0, st, boxes, m, far, prec, pool);
+    hipLaunchKernelGGL(k_build_coupling, dim3(unsigned(n_far)), dim3(kBuildThreads), 0, st, boxes, m, kp, far, prec,
+                       pool);
     return hipGetLastError();
 }
 

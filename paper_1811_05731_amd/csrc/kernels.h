@@ -49,8 +49,8 @@ hipError_t launch_build_wt(DevMesh mesh, const double* boxes, int m, const doubl
                            const LeafDesc* leaves, int64_t n_leaves, int prec, void* pool, hipStream_t st);
 hipError_t launch_build_transfer(const double* boxes, const int32_t* parent, int64_t n_clusters, int m, int prec,
                                  void* e, hipStream_t st);
-hipError_t launch_build_coupling(const double* boxes, int m, const FarDesc* far, int64_t n_far, int prec, void* pool,
-                                 hipStream_t st);
+hipError_t launch_build_coupling(const double* boxes, int m, int kp, const FarDesc* far, int64_t n_far, int prec,
+                                 void* pool, hipStream_t st);
 hipError_t launch_build_near(DevMesh mesh, const NearDesc* near, int64_t n_near, int prec, void* pool,
                              const int64_t* ring_off, const int32_t* ring_pos, double* ns_val, hipStream_t st);
 
@@ -83,6 +83,13 @@ hipError_t launch_unpermute(const double* y64, int io, int64_t n_nodes, int nr, 
 // prefer_rows: split the rows of one item over the 4 waves (else split its blocks)
 hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st);
 hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st);
+// Coupling products; for k <= 128 with ceil(k/16) a power of two the blocks are
+// stored k x coupling_cols(k) (zero columns beyond k) and a pipelined kernel runs.
+hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st);
+inline int coupling_cols(int k) {
+    const int rt = (k + 15) / 16;
+    return (rt <= 8 && (rt & (rt - 1)) == 0) ? 16 * rt : k;
+}
 hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, const int32_t* child1, const void* e,
                          void* xh, int m, int prec, hipStream_t st);
 hipError_t launch_downward(int32_t c_begin, int32_t c_end, const int32_t* parent, const void* e, void* yh, int m,
