@@ -234,17 +234,26 @@ def main():
     op.close()
 
     if not args.no_variants and args.precision == "fp32":
-        op64 = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision="fp64", device=0)
-        ms64, k64 = time_path(op64, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=True)
-        u2_64 = d_u2.cpu().numpy()
-        err = np.max(np.linalg.norm(u2_main - u2_64, axis=1) / np.linalg.norm(u2_64, axis=1))
-        c64_ms, c64_n = k64["coupling"]
-        out["variants"] = {"fp64": {
-            "value": round(n * nrhs / (ms64 * 1e-3) / 1e9, 4), "ms_per_step": round(ms64, 4),
-            "coupling_GBps": round(coupling_alg_bytes(op64.stats, 8) / (c64_ms / max(c64_n, 1) * 1e-3) / 1e9, 1),
-            "apply_hbm_frac": round(apply_alg_bytes(op64.stats, 8, n, nrhs) / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
-        out["fp32_vs_fp64_gpu_rel_err"] = float(f"{err:.3e}")
-        op64.close()
+        variants, outs = {}, {}
+        for prec in ("fp64", "bf16x3"):
+            if prec == "bf16x3" and case.order > 5:
+                continue
+            opv = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0)
+            msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=True)
+            outs[prec] = d_u2.cpu().numpy()
+            ev = 8 if prec == "fp64" else 4
+            cv_ms, cv_n = kv["coupling"]
+            variants[prec] = {
+                "value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
+                "coupling_GBps": round(coupling_alg_bytes(opv.stats, ev) / (cv_ms / max(cv_n, 1) * 1e-3) / 1e9, 1),
+                "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            opv.close()
+        ref = outs["fp64"]
+        rel = lambda a: float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)):.3e}")  # noqa: E731
+        out["fp32_vs_fp64_gpu_rel_err"] = rel(u2_main)
+        if "bf16x3" in outs:
+            variants["bf16x3"]["vs_fp64_gpu_rel_err"] = rel(outs["bf16x3"])
+        out["variants"] = variants
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)        # 1 GiB

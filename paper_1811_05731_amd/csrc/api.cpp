@@ -256,7 +256,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     for (size_t b = 0; b < S.far.size(); ++b)
         far_by_t[h->gid_of_pre[S.far[b].first]].push_back(h->gid_of_pre[S.far[b].second]);
     int64_t off_s = 0;
-    const int kp = coupling_cols(k);
+    const int kp = h->prec == H2DLP_BF16X3 ? bf16x3_cols(k) : coupling_cols(k);
     h->kp = kp;
     for (int32_t g = 0; g < C; ++g) {
         auto& lst = far_by_t[g];
@@ -515,7 +515,7 @@ static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_hand
     if (!(o->alpha >= 0.0 && o->alpha <= 1.0)) return fail(H2DLP_EINVAL, "alpha must be in [0, 1]");
     if (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32 && o->precision != H2DLP_BF16X3)
         return fail(H2DLP_EINVAL, "unknown precision");
-    if (o->precision == H2DLP_BF16X3) return fail(H2DLP_ENOTSUP, "BF16X3 not available in this build");
+    if (o->precision == H2DLP_BF16X3 && o->order > 5) return fail(H2DLP_ENOTSUP, "BF16X3 needs order <= 5 (k <= 128)");
     return H2DLP_OK;
 }
 

@@ -257,15 +257,16 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_coupling(const double* 
             const double dz = pt[2][nu / (m * m)] - ps[2][mu / (m * m)];
             v = 1.0 / (4.0 * kPi * sqrt(dx * dx + dy * dy + dz * dz));
         }
-        const int64_t off = F.a_off + a_offset(k, kp, nu, mu);
         if (prec == P_BF16X3) {
+            // a_off counts 4-byte entries; the pair (hi, lo) of entry (nu, mu) sits in the bf16x3 layout
             const float f = float(v);
-            const __hip_bfloat16 hi = __float2bfloat16(f);
-            const __hip_bfloat16 lo = __float2bfloat16(f - __bfloat162float(hi));
-            static_cast<__hip_bfloat16*>(pool)[2 * off] = hi;
-            static_cast<__hip_bfloat16*>(pool)[2 * off + 1] = lo;
+            const __bf16 hi = __bf16(f);
+            const __bf16 lo = __bf16(f - float(hi));
+            __bf16* base = static_cast<__bf16*>(pool) + 2 * F.a_off;
+            base[bf16x3_offset(k, nu, mu, 0)] = hi;
+            base[bf16x3_offset(k, nu, mu, 1)] = lo;
         } else {
-            put_prec(pool, off, v, prec);
+            put_prec(pool, F.a_off + a_offset(k, kp, nu, mu), v, prec);
         }
     }
 }
