@@ -149,6 +149,17 @@ int h2dlp_export_structure(h2dlp_handle h, int64_t* perm, int64_t* clusters, dou
 /* The diagonal D_ii = Psi_i/(4 pi) - 1 as computed on the device (host array, node order). */
 int h2dlp_export_diagonal(h2dlp_handle h, double* diag);
 
+/* Free the operator's device memory, keeping it in pinned host memory, and
+ * bring it back: an operator evicted to make room for others returns without
+ * a rebuild.  The operator does not change after the build, so the first
+ * offload copies it to the host once and keeps that copy until h2dlp_free;
+ * later offloads only free, reloads copy host to device.  Synchronises the
+ * device.  Apply on an offloaded handle returns EINVAL.  Both are no-ops in the
+ * target state.  Errors: EINVAL (plan-only handle), ENOMEM (pinned host or
+ * device allocation; reload then leaves the handle offloaded), EDEVICE. */
+int h2dlp_offload(h2dlp_handle h);
+int h2dlp_reload(h2dlp_handle h);
+
 void h2dlp_free(h2dlp_handle h);
 
 const char* h2dlp_last_error(void);

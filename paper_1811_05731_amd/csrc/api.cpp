@@ -132,6 +132,10 @@ struct h2dlp_ctx {
     int32_t rt_leaf = 1;
     int kp = 0;                      // stored columns of a coupling block
     bool materialized = false;
+    // offload: device buffers parked in pinned host memory
+    bool offloaded = false;
+    struct Parked { void** field; void* host; size_t bytes; bool scratch; };
+    std::vector<Parked> parked;
     // host-side plan
     std::vector<int32_t> child0, child1, parent;
     std::vector<double> boxes;
@@ -156,7 +160,23 @@ struct h2dlp_ctx {
         (void)hipSetDevice(device);
         for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
+        for (auto& p : parked) if (p.host) (void)hipHostFree(p.host);
         (void)hipSetDevice(cur);
+    }
+
+    // every device pointer the apply reads, with the field that holds it
+    std::vector<std::pair<void**, bool>> fields() {
+        return {{(void**)&d_perm, false}, {(void**)&d_iperm, false}, {(void**)&d_diag, false},
+                {(void**)&d_child0, false}, {(void**)&d_child1, false}, {(void**)&d_parent, false},
+                {(void**)&d_e, false}, {(void**)&d_pool_wt, false}, {(void**)&d_pool_s, false},
+                {(void**)&d_pool_leaf, false}, {(void**)&d_items_fwd, false}, {(void**)&d_blks_fwd, false},
+                {(void**)&d_items_cpl, false}, {(void**)&d_blks_cpl, false}, {(void**)&d_items_leaf, false},
+                {(void**)&d_blks_leaf, false}, {(void**)&d_ns_off, false}, {(void**)&d_ns_pos, false},
+                {(void**)&d_ns_val, false}, {(void**)&d_ws, true}};
+    }
+    size_t bytes_of(void* p) const {
+        for (const auto& b : bufs) if (b.p == p) return b.bytes;
+        return 0;
     }
 
     template <typename P>
@@ -435,6 +455,14 @@ void rec_end(h2dlp_ctx* h, hipStream_t s, int kind, hipEvent_t a) {
 }
 
 int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStream_t s, void* ws) {
+    // every buffer the kernels read must exist (an offloaded operator has none)
+    for (auto& f : h->fields()) {
+        const bool optional = f.first == (void**)&h->d_ns_off || f.first == (void**)&h->d_ns_pos ||
+                              f.first == (void**)&h->d_ns_val;
+        if (*f.first == nullptr && !(optional && h->prec == H2DLP_FP64))
+            return fail(H2DLP_EINVAL, "operator buffers are not on the device");
+    }
+    if (ws == nullptr) return fail(H2DLP_EINVAL, "no workspace");
     const int64_t N = h->S.n_nodes;
     const int m = h->m, k = h->k, prec = h->prec;
     char* base = static_cast<char*>(ws);
@@ -584,6 +612,7 @@ int h2dlp_apply_ex(h2dlp_handle hh, const void* u1, void* u2, int nrhs, int io_d
     if (!u1 || !u2) return fail(H2DLP_EINVAL, "u1 or u2 is NULL");
     if (nrhs < 1) return fail(H2DLP_EINVAL, "nrhs must be >= 1");
     if (!h->materialized) return fail(H2DLP_EINVAL, "handle comes from h2dlp_plan: nothing on the device");
+    if (h->offloaded) return fail(H2DLP_EINVAL, "operator is offloaded: call h2dlp_reload first");
     if (io_dtype != H2DLP_IO_F64 && io_dtype != H2DLP_IO_F32) return fail(H2DLP_EINVAL, "unknown io dtype");
     const size_t bytes = (io_dtype == H2DLP_IO_F32 ? 4 : 8) * size_t(nrhs) * size_t(h->S.n_nodes);
     const char* a = static_cast<const char*>(u1);
@@ -651,11 +680,96 @@ int h2dlp_export_diagonal(h2dlp_handle hh, double* diag) {
     h2dlp_ctx* h = as_ctx(hh);
     if (!h || !diag) return fail(H2DLP_EINVAL, "handle or output is NULL");
     if (!h->materialized) return fail(H2DLP_EINVAL, "handle comes from h2dlp_plan: nothing on the device");
+    if (h->offloaded) return fail(H2DLP_EINVAL, "operator is offloaded: call h2dlp_reload first");
     std::vector<double> d(h->S.n_nodes);
     if (hipSetDevice(h->device) != hipSuccess ||
         hipMemcpy(d.data(), h->d_diag, sizeof(double) * d.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(H2DLP_EDEVICE, "copying the diagonal failed");
     for (int64_t p = 0; p < h->S.n_nodes; ++p) diag[h->S.perm[p]] = d[p];
+    return H2DLP_OK;
+}
+
+int h2dlp_offload(h2dlp_handle hh) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    if (!h->materialized) return fail(H2DLP_EINVAL, "handle comes from h2dlp_plan: nothing on the device");
+    if (h->offloaded) return H2DLP_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (hipSetDevice(h->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
+        return fail(H2DLP_EDEVICE, "synchronising the device before offload failed");
+    // the operator never changes after the build: the first offload keeps a
+    // pinned host copy for good, later offloads only free the device memory
+    if (h->parked.empty()) {
+        std::vector<h2dlp_ctx::Parked> parked;
+        int rc = H2DLP_OK;
+        for (auto& f : h->fields()) {
+            void* p = *f.first;
+            if (!p) continue;
+            const size_t bytes = h->bytes_of(p);
+            void* host = nullptr;
+            if (!f.second) {
+                if (hipHostMalloc(&host, bytes, hipHostMallocDefault) != hipSuccess) {
+                    rc = fail(H2DLP_ENOMEM, "pinned host allocation failed");
+                    break;
+                }
+                if (hipMemcpy(host, p, bytes, hipMemcpyDeviceToHost) != hipSuccess) {
+                    (void)hipHostFree(host);
+                    rc = fail(H2DLP_EDEVICE, "copy to host failed");
+                    break;
+                }
+            }
+            parked.push_back({f.first, host, bytes, f.second});
+        }
+        if (rc != H2DLP_OK) {
+            for (auto& p : parked) if (p.host) (void)hipHostFree(p.host);
+            (void)hipSetDevice(cur);
+            return rc;
+        }
+        h->parked = std::move(parked);
+    }
+    for (auto& p : h->parked) {
+        h->release(*p.field);
+        *p.field = nullptr;
+    }
+    h->offloaded = true;
+    (void)hipSetDevice(cur);
+    return H2DLP_OK;
+}
+
+int h2dlp_reload(h2dlp_handle hh) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    if (!h->offloaded) return H2DLP_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (hipSetDevice(h->device) != hipSuccess) return fail(H2DLP_EDEVICE, "hipSetDevice failed");
+    int rc = H2DLP_OK;
+    size_t done = 0;
+    try {
+        for (; done < h->parked.size(); ++done) {
+            auto& p = h->parked[done];
+            void* d = h->alloc<void>(p.bytes, nullptr);
+            *p.field = d;
+            if (!p.scratch && hipMemcpy(d, p.host, p.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+                ++done;
+                rc = fail(H2DLP_EDEVICE, "copy to device failed");
+                break;
+            }
+        }
+    } catch (const std::bad_alloc&) {
+        rc = fail(H2DLP_ENOMEM, "device allocation failed during reload");
+    }
+    if (rc != H2DLP_OK) {           // back to the offloaded state
+        for (size_t q = 0; q < done && q < h->parked.size(); ++q) {
+            h->release(*h->parked[q].field);
+            *h->parked[q].field = nullptr;
+        }
+        (void)hipSetDevice(cur);
+        return rc;
+    }
+    h->offloaded = false;
+    (void)hipSetDevice(cur);
     return H2DLP_OK;
 }
 

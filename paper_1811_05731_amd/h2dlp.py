@@ -56,7 +56,8 @@ class _Stats(ctypes.Structure):
 
 
 EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
-            "h2dlp_bytes", "h2dlp_info", "h2dlp_export_structure", "h2dlp_export_diagonal", "h2dlp_free",
+            "h2dlp_bytes", "h2dlp_info", "h2dlp_export_structure", "h2dlp_export_diagonal", "h2dlp_offload",
+            "h2dlp_reload", "h2dlp_free",
             "h2dlp_last_error", "h2dlp_profile", "h2dlp_profile_read")
 
 
@@ -89,6 +90,10 @@ def _load():
     lib.h2dlp_export_structure.restype = I
     lib.h2dlp_export_diagonal.argtypes = [V, P(D)]
     lib.h2dlp_export_diagonal.restype = I
+    lib.h2dlp_offload.argtypes = [V]
+    lib.h2dlp_offload.restype = I
+    lib.h2dlp_reload.argtypes = [V]
+    lib.h2dlp_reload.restype = I
     lib.h2dlp_free.argtypes = [V]
     lib.h2dlp_free.restype = None
     lib.h2dlp_last_error.argtypes = []
@@ -227,6 +232,14 @@ class Operator:
         d = np.empty(self.n_nodes, np.float64)
         _check(_lib.h2dlp_export_diagonal(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return d
+
+    def offload(self):
+        """Park the operator in pinned host memory and free its HBM."""
+        _check(_lib.h2dlp_offload(self._h))
+
+    def reload(self):
+        """Bring an offloaded operator back to the device."""
+        _check(_lib.h2dlp_reload(self._h))
 
     def profile(self, enable: bool = True):
         _check(_lib.h2dlp_profile(self._h, int(enable)))

@@ -1,0 +1,367 @@
+"""Continuous-batching service of boundary-operator matvec requests.
+
+A request asks for u2 = M u1 on one of several meshes (Section 3, eq. denseMat:
+in a micromagnetic run every effective-field evaluation needs one such product,
+Section 1).  The server keeps operators resident on the GPU within an HBM
+budget, coalesces the queued requests of one mesh into one multi-column apply,
+runs up to `n_slots` applies at once on their own streams with their own
+workspaces, and admits new work whenever a slot frees up -- requests that
+arrive while others are on the GPU join the next batch of their mesh.
+Operators that do not fit are made room for by parking idle ones in pinned
+host memory (least recently used first) and reloading them later.
+
+The scheduler is independent of the GPU: `Backend` is the interface it drives.
+`GpuBackend` implements it on the HIP library; tests drive the same scheduler
+with a CPU stand-in.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Any, Optional
+
+import numpy as np
+
+__all__ = ["MeshSpec", "Request", "Backend", "GpuBackend", "Server", "percentile"]
+
+
+@dataclass
+class MeshSpec:
+    mesh_id: str
+    xyz: np.ndarray
+    tri: np.ndarray
+    order: int = 4
+    leaf: int = 64
+    eta: float = 2.0
+    precision: str = "fp32"
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.xyz.shape[0])
+
+
+@dataclass
+class Request:
+    rid: int
+    mesh_id: str
+    u1: np.ndarray                 # (r, N) float64, caller's node order
+    arrival: float = 0.0           # seconds after the start of Server.run
+    result: Optional[np.ndarray] = None
+    error: Optional[str] = None
+    done: Optional[float] = None   # seconds after the start of Server.run
+    batch_id: Optional[int] = None
+
+    @property
+    def nrhs(self) -> int:
+        return int(np.atleast_2d(self.u1).shape[0])
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done is None else self.done - self.arrival
+
+
+class Backend:
+    """What the scheduler needs from an execution engine."""
+
+    def plan_bytes(self, spec: MeshSpec) -> tuple:             # (resident, workspace) bytes
+        raise NotImplementedError
+
+    def build(self, spec: MeshSpec) -> Any:
+        raise NotImplementedError
+
+    def offload(self, op) -> None:
+        raise NotImplementedError
+
+    def reload(self, op) -> None:
+        raise NotImplementedError
+
+    def free(self, op) -> None:
+        raise NotImplementedError
+
+    def make_slots(self, n: int, workspace_bytes: int) -> list:
+        raise NotImplementedError
+
+    def launch(self, slot, op, u1: np.ndarray) -> Any:       # -> ticket
+        raise NotImplementedError
+
+    def poll(self, ticket) -> bool:
+        raise NotImplementedError
+
+    def collect(self, ticket) -> np.ndarray:
+        raise NotImplementedError
+
+
+class GpuBackend(Backend):
+    """The HIP library on one GPU: torch supplies streams, pinned staging and workspaces."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        from . import h2dlp
+        self.torch = torch
+        self.h2dlp = h2dlp
+        self.device = torch.device("cuda", device)
+        self.dev_index = device
+
+    def plan_bytes(self, spec):
+        p = self.h2dlp.plan(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision)
+        return p.stats.bytes_resident, p.stats.workspace_bytes
+
+    def build(self, spec):
+        return self.h2dlp.Operator(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
+                                   device=self.dev_index)
+
+    def offload(self, op):
+        op.offload()
+
+    def reload(self, op):
+        op.reload()
+
+    def free(self, op):
+        op.close()
+
+    def make_slots(self, n, workspace_bytes):
+        t = self.torch
+        return [{"stream": t.cuda.Stream(device=self.device),
+                 "ws": t.empty(max(1, workspace_bytes), dtype=t.uint8, device=self.device)} for _ in range(n)]
+
+    def launch(self, slot, op, u1):
+        t = self.torch
+        s = slot["stream"]
+        host = t.from_numpy(np.ascontiguousarray(u1, dtype=np.float64)).pin_memory()
+        with t.cuda.stream(s):
+            d1 = t.empty(host.shape, dtype=t.float64, device=self.device)
+            d1.copy_(host, non_blocking=True)
+            d2 = t.empty_like(d1)
+            op.apply(d1, d2, stream=s, workspace=slot["ws"])
+            out = t.empty(host.shape, dtype=t.float64, pin_memory=True)
+            out.copy_(d2, non_blocking=True)
+            ev = t.cuda.Event()
+            ev.record(s)
+        return (ev, out, host, d1, d2)
+
+    def poll(self, ticket):
+        return ticket[0].query()
+
+    def collect(self, ticket):
+        ticket[0].synchronize()
+        return ticket[1].numpy().copy()
+
+
+@dataclass
+class _Mesh:
+    spec: MeshSpec
+    resident_bytes: int
+    workspace_bytes: int
+    op: Any = None
+    on_device: bool = False
+    inflight: int = 0
+    last_used: float = 0.0
+    queue: deque = field(default_factory=deque)
+    builds: int = 0
+    reloads: int = 0
+    offloads: int = 0
+
+
+def percentile(values, q: float) -> float:
+    v = np.sort(np.asarray(values, dtype=np.float64))
+    if v.size == 0:
+        return float("nan")
+    return float(np.percentile(v, q))
+
+
+class Server:
+    """Continuous batching over resident operators within an HBM budget."""
+
+    def __init__(self, backend: Backend, budget_bytes: int, n_slots: int = 4, max_batch_rhs: int = 64,
+                 aging: float = 0.05, clock=time.perf_counter):
+        if n_slots < 1 or max_batch_rhs < 1:
+            raise ValueError("n_slots and max_batch_rhs must be >= 1")
+        self.backend = backend
+        self.budget = int(budget_bytes)
+        self.n_slots = n_slots
+        self.max_batch_rhs = max_batch_rhs
+        self.aging = aging
+        self.clock = clock
+        self.t0 = 0.0
+        self.meshes: dict = {}
+        self.slots = None
+        self.free_slots = []
+        self.inflight = []                 # (ticket, slot, mesh, [requests], column offsets)
+        self.batches = 0
+        self.rejected = 0
+
+    # -- registration and memory ----------------------------------------------------
+    def add_mesh(self, spec: MeshSpec):
+        resident, ws = self.backend.plan_bytes(spec)
+        self.meshes[spec.mesh_id] = _Mesh(spec, int(resident), int(ws))
+
+    def _slot_bytes(self) -> int:
+        return self.n_slots * max((m.workspace_bytes for m in self.meshes.values()), default=0)
+
+    def _used(self) -> int:
+        return self._slot_bytes() + sum(m.resident_bytes for m in self.meshes.values() if m.on_device)
+
+    def _fits(self, m: _Mesh) -> bool:
+        return self._slot_bytes() + m.resident_bytes <= self.budget
+
+    def _make_resident(self, m: _Mesh) -> bool:
+        """Evict idle operators (least recently used first) until m fits; then build or reload it."""
+        if m.on_device:
+            return True
+        while self._used() + m.resident_bytes > self.budget:
+            idle = [x for x in self.meshes.values() if x.on_device and x.inflight == 0 and x is not m]
+            if not idle:
+                return False
+            victim = min(idle, key=lambda x: x.last_used)
+            self.backend.offload(victim.op)
+            victim.on_device = False
+            victim.offloads += 1
+        if m.op is None:
+            m.op = self.backend.build(m.spec)
+            m.builds += 1
+        else:
+            self.backend.reload(m.op)
+            m.reloads += 1
+        m.on_device = True
+        return True
+
+    def prewarm(self):
+        """Build every registered operator once (a geometry's operator is set up
+        before its first request); operators beyond the budget end up offloaded."""
+        for m in self.meshes.values():
+            if m.op is None and self._fits(m):
+                self._make_resident(m)
+
+    # -- the loop -------------------------------------------------------------------
+    def _reject(self, req: Request, msg: str):
+        req.error = msg
+        req.done = self.clock() - self.t0
+        self.rejected += 1
+
+    def _accept(self, req: Request):
+        m = self.meshes.get(req.mesh_id)
+        u = np.atleast_2d(req.u1)
+        if m is None:
+            return self._reject(req, f"unknown mesh {req.mesh_id!r}")
+        if u.ndim != 2 or u.shape[1] != m.spec.n_nodes or u.shape[0] < 1:
+            return self._reject(req, f"u1 must have shape (r, {m.spec.n_nodes})")
+        if not np.all(np.isfinite(u)):
+            return self._reject(req, "u1 has non-finite values")
+        if not self._fits(m):
+            return self._reject(req, "operator larger than the HBM budget")
+        m.queue.append(req)
+
+    def _launch_ready(self, now: float) -> bool:
+        launched = False
+        while self.free_slots:
+            waiting = [m for m in self.meshes.values() if m.queue]
+            if not waiting:
+                break
+            # resident meshes first (no load cost) unless a head request has
+            # waited longer than `aging`, then the oldest head request first
+            waiting.sort(key=lambda m: (not m.on_device and now - m.queue[0].arrival < self.aging,
+                                        m.queue[0].arrival))
+            started = False
+            for m in waiting:
+                try:
+                    ok = self._make_resident(m)
+                except Exception as e:  # build / reload failure: fail this mesh's queue
+                    while m.queue:
+                        self._reject(m.queue.popleft(), f"could not make operator resident: {e}")
+                    continue
+                if not ok:
+                    continue
+                batch, cols = [], 0
+                while m.queue and (not batch or cols + m.queue[0].nrhs <= self.max_batch_rhs):
+                    r = m.queue.popleft()
+                    batch.append(r)
+                    cols += r.nrhs
+                u = np.concatenate([np.atleast_2d(r.u1) for r in batch], axis=0)
+                slot = self.free_slots.pop()
+                try:
+                    ticket = self.backend.launch(slot, m.op, u)
+                except Exception as e:
+                    self.free_slots.append(slot)
+                    for r in batch:
+                        self._reject(r, f"apply failed: {e}")
+                    continue
+                self.batches += 1
+                for r in batch:
+                    r.batch_id = self.batches
+                m.inflight += 1
+                m.last_used = now
+                self.inflight.append((ticket, slot, m, batch))
+                started = launched = True
+                break
+            if not started:
+                break
+        return launched
+
+    def _reap(self) -> bool:
+        reaped = False
+        keep = []
+        for ticket, slot, m, batch in self.inflight:
+            if self.backend.poll(ticket):
+                out = self.backend.collect(ticket)
+                t = self.clock()
+                c = 0
+                for r in batch:
+                    r.result = out[c:c + r.nrhs]
+                    r.done = t - self.t0
+                    c += r.nrhs
+                m.inflight -= 1
+                self.free_slots.append(slot)
+                reaped = True
+            else:
+                keep.append((ticket, slot, m, batch))
+        self.inflight = keep
+        return reaped
+
+    def run(self, requests, idle_sleep: float = 5e-5) -> dict:
+        """Serve `requests` (Request objects with arrival times relative to the start)."""
+        if self.slots is None:
+            self.slots = self.backend.make_slots(self.n_slots, max((m.workspace_bytes for m in self.meshes.values()),
+                                                                   default=1))
+            self.free_slots = list(self.slots)
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        self.t0 = self.clock()
+        start = time.perf_counter()
+        while pending or self.inflight or any(m.queue for m in self.meshes.values()):
+            now = self.clock() - self.t0
+            progressed = False
+            while pending and pending[0].arrival <= now:
+                self._accept(pending.popleft())
+                progressed = True
+            progressed |= self._reap()
+            progressed |= self._launch_ready(now)
+            if not progressed:
+                if pending and not self.inflight and not any(m.queue for m in self.meshes.values()):
+                    time.sleep(max(0.0, min(pending[0].arrival - (self.clock() - self.t0), 0.01)))
+                else:
+                    time.sleep(idle_sleep)
+        wall = time.perf_counter() - start
+        ok = [r for r in requests if r.error is None]
+        lat = [r.latency for r in ok]
+        cols = sum(r.nrhs for r in ok)
+        dofs = sum(r.nrhs * self.meshes[r.mesh_id].spec.n_nodes for r in ok)
+        return {
+            "requests": len(requests), "served": len(ok), "rejected": len(requests) - len(ok),
+            "batches": self.batches, "wall_s": wall,
+            "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
+            "max_ms": 1e3 * (max(lat) if lat else float("nan")),
+            "throughput_req_s": len(ok) / wall if wall > 0 else float("nan"),
+            "throughput_rhs_s": cols / wall if wall > 0 else float("nan"),
+            "throughput_GDOF_s": dofs / wall / 1e9 if wall > 0 else float("nan"),
+            "builds": {k: m.builds for k, m in self.meshes.items()},
+            "reloads": {k: m.reloads for k, m in self.meshes.items()},
+            "offloads": {k: m.offloads for k, m in self.meshes.items()},
+        }
+
+    def close(self):
+        for m in self.meshes.values():
+            if m.op is not None:
+                self.backend.free(m.op)
+                m.op = None
+                m.on_device = False

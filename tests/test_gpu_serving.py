@@ -1,0 +1,75 @@
+"""Serving on the GPU: results in the mix are the results alone, under an HBM
+budget that forces operators out of and back into device memory."""
+import numpy as np
+import pytest
+
+from workloads import meshes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1811_05731_amd import h2dlp, serving
+    return h2dlp, serving
+
+
+def _meshes():
+    return {"sphere": meshes.icosphere(3, 0.01, 0), "torus": meshes.torus(1.0, 0.3, 48, 16),
+            "film": meshes.cuboid(60.0, 40.0, 10.0, 5.0, 0.5, 0)}
+
+
+def _apply(op, u):
+    d1 = torch.tensor(np.atleast_2d(u), device="cuda")
+    d2 = torch.empty_like(d1)
+    op.apply(d1, d2)
+    torch.cuda.synchronize()
+    return d2.cpu().numpy()
+
+
+def test_offload_reload_roundtrip(mods):
+    h2dlp, _ = mods
+    xyz, tri = meshes.icosphere(3, 0.01, 0)
+    op = h2dlp.Operator(xyz, tri, order=4, leaf=32, precision="fp32")
+    u = np.random.default_rng(0).normal(size=(5, xyz.shape[0]))
+    before = _apply(op, u)
+    for _ in range(2):
+        op.offload()
+        with pytest.raises(h2dlp.H2dlpError):
+            _apply(op, u)
+        op.reload()
+        assert np.array_equal(_apply(op, u), before)
+
+
+def test_mix_equals_alone_under_budget(mods):
+    h2dlp, serving = mods
+    ms = _meshes()
+    specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32") for k, (x, t) in ms.items()]
+    backend = serving.GpuBackend(0)
+    sizes = {s.mesh_id: backend.plan_bytes(s) for s in specs}
+    n_slots = 3
+    slot_bytes = n_slots * max(w for _, w in sizes.values())
+    res = sorted(r for r, _ in sizes.values())
+    budget = slot_bytes + res[-1] + res[-2] - 1          # never all three at once
+    srv = serving.Server(backend, budget, n_slots=n_slots, max_batch_rhs=24)
+    for s in specs:
+        srv.add_mesh(s)
+    srv.prewarm()
+    g = np.random.default_rng(4)
+    t = np.cumsum(g.exponential(1 / 400.0, 60))
+    names = list(ms)
+    reqs = []
+    for q in range(60):
+        name = names[g.integers(3)]
+        reqs.append(serving.Request(q, name, g.normal(size=(int(g.integers(1, 9)), ms[name][0].shape[0])),
+                                    float(t[q])))
+    stats = srv.run(reqs)
+    assert stats["served"] == 60, [r.error for r in reqs if r.error]
+    assert sum(stats["offloads"].values()) > 0 and sum(stats["reloads"].values()) > 0
+    assert stats["batches"] < 60
+    alone_ops = {s.mesh_id: h2dlp.Operator(s.xyz, s.tri, s.order, s.leaf, s.eta, s.precision) for s in specs}
+    for r in reqs:
+        assert np.array_equal(r.result, _apply(alone_ops[r.mesh_id], r.u1)), r.rid
+    srv.close()
