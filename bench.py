@@ -157,6 +157,46 @@ def cpu_baseline(xyz, tri, case, nrhs: int, frac: float = 0.01, seed: int = 7) -
     }
 
 
+def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4) -> dict:
+    """The serving mix: Poisson arrivals of 1..16-column requests over six resident meshes.
+
+    Spheres (levels 4-7), the thin film and a torus, FP32 operators; the HBM
+    budget holds the largest operator plus the slot workspaces but not all
+    operators at once, so idle ones are offloaded and reloaded.
+    """
+    from paper_1811_05731_amd import serving
+    from workloads import cases, rhs
+
+    backend = serving.GpuBackend(0)
+    specs = []
+    for spec, order, leaf in cases.SERVING_MESHES:
+        xyz, tri = cases.mesh_of(spec)
+        specs.append(serving.MeshSpec(spec.name, xyz, tri, order=order, leaf=leaf, eta=2.0, precision="fp32"))
+    sizes = [backend.plan_bytes(s) for s in specs]
+    resident = [r for r, _ in sizes]
+    slot_bytes = n_slots * max(w for _, w in sizes)
+    budget = slot_bytes + max(max(resident), int(0.9 * sum(resident)))
+    srv = serving.Server(backend, budget, n_slots=n_slots, max_batch_rhs=64)
+    for s in specs:
+        srv.add_mesh(s)
+    t0 = time.perf_counter()
+    srv.prewarm()
+    prewarm_s = time.perf_counter() - t0
+    reqs = []
+    for q, (arr, mi, nr, seed) in enumerate(rhs.poisson_requests(n_requests, rate_hz, len(specs), 16, seed=1)):
+        s = specs[mi]
+        reqs.append(serving.Request(q, s.mesh_id, np.random.default_rng(seed).normal(size=(nr, s.n_nodes)), arr))
+    st = srv.run(reqs)
+    srv.close()
+    return {"requests": st["requests"], "served": st["served"], "p50_ms": round(st["p50_ms"], 3),
+            "p99_ms": round(st["p99_ms"], 3), "max_ms": round(st["max_ms"], 3),
+            "throughput_req_s": round(st["throughput_req_s"], 2),
+            "throughput_GDOF_s": round(st["throughput_GDOF_s"], 4), "batches": st["batches"],
+            "budget_GB": round(budget / 1e9, 2), "operators_GB": round(sum(resident) / 1e9, 2),
+            "slots": n_slots, "precision": "fp32", "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
+            "reloads": sum(st["reloads"].values()), "offloads": sum(st["offloads"].values())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +207,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the FP64 comparison path")
     ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -254,6 +295,10 @@ def main():
         if "bf16x3" in outs:
             variants["bf16x3"]["vs_fp64_gpu_rel_err"] = rel(outs["bf16x3"])
         out["variants"] = variants
+
+    if not args.no_serve:
+        print("# serving the mixed request stream", file=sys.stderr, flush=True)
+        out["serving"] = serve_bench()
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)        # 1 GiB

@@ -175,7 +175,7 @@ class Server:
     """Continuous batching over resident operators within an HBM budget."""
 
     def __init__(self, backend: Backend, budget_bytes: int, n_slots: int = 4, max_batch_rhs: int = 64,
-                 aging: float = 0.05, clock=time.perf_counter):
+                 aging: float = 0.05, reload_bytes_per_s: float = 20e9, clock=time.perf_counter):
         if n_slots < 1 or max_batch_rhs < 1:
             raise ValueError("n_slots and max_batch_rhs must be >= 1")
         self.backend = backend
@@ -183,6 +183,7 @@ class Server:
         self.n_slots = n_slots
         self.max_batch_rhs = max_batch_rhs
         self.aging = aging
+        self.reload_bytes_per_s = reload_bytes_per_s
         self.clock = clock
         self.t0 = 0.0
         self.meshes: dict = {}
@@ -205,6 +206,9 @@ class Server:
 
     def _fits(self, m: _Mesh) -> bool:
         return self._slot_bytes() + m.resident_bytes <= self.budget
+
+    def _patience(self, m: _Mesh) -> float:
+        return self.aging + 2.0 * m.resident_bytes / self.reload_bytes_per_s
 
     def _make_resident(self, m: _Mesh) -> bool:
         """Evict idle operators (least recently used first) until m fits; then build or reload it."""
@@ -259,9 +263,10 @@ class Server:
             waiting = [m for m in self.meshes.values() if m.queue]
             if not waiting:
                 break
-            # resident meshes first (no load cost) unless a head request has
-            # waited longer than `aging`, then the oldest head request first
-            waiting.sort(key=lambda m: (not m.on_device and now - m.queue[0].arrival < self.aging,
+            # resident meshes first (no load cost); a non-resident mesh goes
+            # first once its head request has waited longer than `aging` plus
+            # twice its estimated reload time; then the oldest head request
+            waiting.sort(key=lambda m: (not m.on_device and now - m.queue[0].arrival < self._patience(m),
                                         m.queue[0].arrival))
             started = False
             for m in waiting:
