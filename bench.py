@@ -44,9 +44,34 @@ def workload(name: str):
     return c, xyz, tri
 
 
-def coupling_alg_bytes(st, elem: int) -> int:
-    """Algorithmic bytes of one coupling launch: every S_ts once, xhat read once, yhat written once."""
-    return st.coupling_entries * elem + 2 * st.n_clusters * st.k * 16 * elem
+def case_rhs(case, xyz):
+    """The right-hand sides each workload is quoted with, and their description."""
+    from workloads import rhs
+    n = xyz.shape[0]
+    if case.name == "film":
+        return rhs.smooth_fields(xyz, case.nrhs), f"{case.nrhs} smooth fields (16 sinusoids, wavelengths 50-2000 nm)"
+    if case.name in ("sphere_l4", "sphere_l7"):
+        return (np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(n, case.nrhs - 1, 0)]),
+                f"u1 = z and {case.nrhs - 1} N(0,1) right-hand sides")
+    return rhs.normal_rhs(n, case.nrhs, 0), f"{case.nrhs} N(0,1) right-hand sides"
+
+
+def describe(case, n, n_tri, rhs_text):
+    m = case.mesh
+    if m.kind == "icosphere":
+        geo = f"icosphere level {m.level}, radial jitter +-{m.jitter:g}"
+    elif m.kind == "cuboid":
+        geo = f"thin-film cuboid 2000 x 2000 x 20 nm on a 5 nm grid, in-plane jitter +-{m.jitter:g} nm"
+    else:
+        geo = m.kind
+    return (f"{case.name}: {geo}, {n} boundary nodes, {n_tri} triangles, order {case.order}, leaf {case.leaf}, "
+            f"eta {case.eta:g}, {rhs_text}")
+
+
+def coupling_alg_bytes(st, elem_s: int, elem_v: int) -> int:
+    """Algorithmic bytes of one coupling launch: every S_ts once (elem_s bytes
+    per entry), xhat read once and yhat written once (elem_v bytes per value)."""
+    return st.coupling_entries * elem_s + 2 * st.n_clusters * st.k * 16 * elem_v
 
 
 def apply_alg_bytes(st, elem: int, n_nodes: int, nrhs: int, io_elem: int = 8) -> int:
@@ -56,13 +81,15 @@ def apply_alg_bytes(st, elem: int, n_nodes: int, nrhs: int, io_elem: int = 8) ->
     return operator + vectors
 
 
-def time_path(op, d_u1, d_u2, steps: int, warmup: int, profile: bool):
+def time_path(op, d_u1, d_u2, steps: int, warmup: int, profile):
+    """Mean ms per apply over `steps` applies; `profile` = kinds whose launches
+    are timed with HIP events inside the same region (None = none)."""
     import torch
     for _ in range(warmup):
         op.apply(d_u1, d_u2)
     torch.cuda.synchronize()
     if profile:
-        op.profile(True)
+        op.profile(profile)
         op.profile_read(reset=True)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -78,6 +105,45 @@ def time_path(op, d_u1, d_u2, steps: int, warmup: int, profile: bool):
         kernels = op.profile_read(reset=True)
         op.profile(False)
     return ms, kernels
+
+
+def copy_bandwidth(dev, reps: int = 10) -> float:
+    """Device-to-device copy of 1 GiB: bytes read + written per second (GB/s)."""
+    import torch
+    a = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def sphere_check(op, xyz, dev) -> dict:
+    """u1 = z on the unit sphere: u2 should be -2z/3 (demagnetising factor 1/3),
+    and u1 = 1 gives u2 = -1.  Also the same with the smooth-surface diagonal
+    -1/2 in place of Psi/(4 pi) - 1, for comparison."""
+    import torch
+    z = xyz[:, 2]
+    d1 = torch.tensor(np.vstack([z, np.ones_like(z)]), device=dev)
+    d2 = torch.empty_like(d1)
+    op.apply(d1, d2)
+    torch.cuda.synchronize()
+    u2 = d2.cpu().numpy()
+    diag = op.export_diagonal()
+    exact = -2.0 * z / 3.0
+    half = u2[0] - diag * z - 0.5 * z
+    rel = lambda a: float(f"{np.linalg.norm(a - exact) / np.linalg.norm(exact):.3e}")  # noqa: E731
+    return {"u1_z_rel_err": rel(u2[0]), "u1_z_rel_err_half_identity": rel(half),
+            "u1_one_max_err": float(f"{np.max(np.abs(u2[1] + 1.0)):.3e}")}
 
 
 def cpu_baseline(xyz, tri, case, nrhs: int, frac: float = 0.01, seed: int = 7) -> dict:
@@ -172,13 +238,14 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4)
     for spec, order, leaf in cases.SERVING_MESHES:
         xyz, tri = cases.mesh_of(spec)
         specs.append(serving.MeshSpec(spec.name, xyz, tri, order=order, leaf=leaf, eta=2.0, precision="fp32"))
-    sizes = [backend.plan_bytes(s) for s in specs]
-    resident = [r for r, _ in sizes]
-    slot_bytes = n_slots * max(w for _, w in sizes)
-    budget = slot_bytes + max(max(resident), int(0.9 * sum(resident)))
-    srv = serving.Server(backend, budget, n_slots=n_slots, max_batch_rhs=64)
+    srv = serving.Server(backend, 0, n_slots=n_slots, max_batch_rhs=64)
     for s in specs:
         srv.add_mesh(s)
+    resident = [m.resident_bytes for m in srv.meshes.values()]
+    # the film alone is ~80 % of all operators: a budget below 90 % would hold
+    # the film and nothing else, so every switch to or from it would reload it
+    budget = srv.fixed_bytes() + max(max(resident), int(0.9 * sum(resident)))
+    srv.budget = budget
     t0 = time.perf_counter()
     srv.prewarm()
     prewarm_s = time.perf_counter() - t0
@@ -193,6 +260,7 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4)
             "throughput_req_s": round(st["throughput_req_s"], 2),
             "throughput_GDOF_s": round(st["throughput_GDOF_s"], 4), "batches": st["batches"],
             "budget_GB": round(budget / 1e9, 2), "operators_GB": round(sum(resident) / 1e9, 2),
+            "slots_GB": round(srv.fixed_bytes() / 1e9, 2),
             "slots": n_slots, "precision": "fp32", "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
             "reloads": sum(st["reloads"].values()), "offloads": sum(st["offloads"].values())}
 
@@ -218,12 +286,11 @@ def main():
     import torch
 
     from paper_1811_05731_amd import h2dlp
-    from workloads import rhs
 
     case, xyz, tri = workload(args.workload)
     n = xyz.shape[0]
     nrhs = case.nrhs
-    u1 = rhs.normal_rhs(n, nrhs, 0)
+    u1, rhs_text = case_rhs(case, xyz)
     dev = torch.device("cuda:0")
     d_u1 = torch.tensor(u1, device=dev)
     d_u2 = torch.empty_like(d_u1)
@@ -237,12 +304,16 @@ def main():
     print(f"# built {case.name} {args.precision}: N={n} clusters={st.n_clusters} far={st.n_far} near={st.n_near} "
           f"resident={st.bytes_resident / 1e9:.2f} GB in {build_s:.1f} s", file=sys.stderr, flush=True)
 
-    ms, kernels = time_path(op, d_u1, d_u2, args.steps, args.warmup, profile=True)
+    # timed region: HIP events around the coupling launches only (the roofline
+    # kernel); the per-kind breakdown comes from a separate profiled pass
+    ms, kernels = time_path(op, d_u1, d_u2, args.steps, args.warmup, profile=("coupling",))
     u2_main = d_u2.cpu().numpy()
+    _, breakdown = time_path(op, d_u1, d_u2, 5, 0, profile=True)
+    diag_main = op.export_diagonal()
     value = n * nrhs / (ms * 1e-3) / 1e9
     cpl_ms, cpl_n = kernels["coupling"]
     cpl_avg_ms = cpl_ms / max(cpl_n, 1)
-    b_cpl = coupling_alg_bytes(st, elem)
+    b_cpl = coupling_alg_bytes(st, elem, elem)
     achieved = b_cpl / (cpl_avg_ms * 1e-3) / 1e9
     b_apply = apply_alg_bytes(st, elem, n, nrhs)
     traffic = None
@@ -255,45 +326,57 @@ def main():
         "metric": METRIC, "value": round(value, 4), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": f"{case.name}: icosphere level {case.mesh.level}, {n} boundary nodes, "
-                               f"{tri.shape[0]} triangles, radial jitter +-{case.mesh.jitter:g}, order {case.order}, "
-                               f"leaf {case.leaf}, eta {case.eta:g}, {nrhs} N(0,1) right-hand sides",
+        "config": {"workload": describe(case, n, tri.shape[0], rhs_text),
                    "nodes": n, "rhs": nrhs, "order": case.order, "leaf": case.leaf, "eta": case.eta,
                    "precision": args.precision},
         "roofline": {"bound": "hbm", "kernel": "coupling", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "alg_bytes_per_launch": b_cpl, "avg_launch_ms": round(cpl_avg_ms, 4)},
         "apply_hbm_frac": round(b_apply / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        "copy_GBps": None,
         "apply_alg_bytes": b_apply,
-        "kernel_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in kernels.items()},
+        "kernel_ms_per_apply": {k: round(v[0] / 5, 4) for k, v in breakdown.items()},
         "operator": {"clusters": st.n_clusters, "far_blocks": st.n_far, "near_blocks": st.n_near,
                      "coupling_bytes": st.bytes_coupling, "near_bytes": st.bytes_near,
                      "resident_bytes": st.bytes_resident, "compression": round(st.compression, 5),
+                     "bytes_per_dof": round(st.bytes_resident / n, 1),
                      "build_s": round(build_s, 2)},
         "kernel_hash": kernel_hash(),
     }
+    if getattr(case.mesh, "kind", "") == "icosphere":
+        out["sphere_check"] = sphere_check(op, xyz, dev)
     op.close()
+    copy_gbs = copy_bandwidth(dev)
+    out["copy_GBps"] = round(copy_gbs, 1)
+    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    out["apply_copy_frac"] = round(b_apply / (ms * 1e-3) / 1e9 / copy_gbs, 4)
 
     if not args.no_variants and args.precision == "fp32":
         variants, outs = {}, {}
-        for prec in ("fp64", "bf16x3"):
-            if prec == "bf16x3" and case.order > 5:
+        for prec in ("fp64", "bf16x3", "bf16x6"):
+            if prec.startswith("bf16") and case.order > 5:
                 continue
             opv = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0)
-            msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=True)
+            msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=("coupling",))
             outs[prec] = d_u2.cpu().numpy()
-            ev = 8 if prec == "fp64" else 4
+            ev = 8 if prec == "fp64" else 4                      # bytes per vector value
+            es = {"fp64": 8, "bf16x6": 6}.get(prec, 4)            # bytes per coupling entry
             cv_ms, cv_n = kv["coupling"]
             variants[prec] = {
                 "value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
-                "coupling_GBps": round(coupling_alg_bytes(opv.stats, ev) / (cv_ms / max(cv_n, 1) * 1e-3) / 1e9, 1),
+                "coupling_GBps": round(coupling_alg_bytes(opv.stats, es, ev) / (cv_ms / max(cv_n, 1) * 1e-3) / 1e9, 1),
                 "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
             opv.close()
         ref = outs["fp64"]
         rel = lambda a: float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)):.3e}")  # noqa: E731
         out["fp32_vs_fp64_gpu_rel_err"] = rel(u2_main)
-        if "bf16x3" in outs:
-            variants["bf16x3"]["vs_fp64_gpu_rel_err"] = rel(outs["bf16x3"])
+        # the same error relative to |K u1| (the far-reaching part, without the diagonal)
+        k_ref = ref - diag_main[None, :] * u1
+        out["fp32_vs_fp64_gpu_rel_err_of_K"] = float(
+            f"{np.max(np.linalg.norm(u2_main - ref, axis=1) / np.linalg.norm(k_ref, axis=1)):.3e}")
+        for prec in ("bf16x3", "bf16x6"):
+            if prec in outs:
+                variants[prec]["vs_fp64_gpu_rel_err"] = rel(outs[prec])
         out["variants"] = variants
 
     if not args.no_serve:

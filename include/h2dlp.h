@@ -43,6 +43,7 @@ extern "C" {
 #define H2DLP_FP64    0    /* everything in FP64 */
 #define H2DLP_FP32    1    /* FP32 storage and accumulation; FP64 diagonal and near-singular entries */
 #define H2DLP_BF16X3  2    /* as FP32, coupling products as split bf16 x3 on MFMA, FP32 accumulation */
+#define H2DLP_BF16X6  3    /* as BF16X3 with three-term splits and six products (6 bytes per coupling entry) */
 
 /* element type of u1 / u2 */
 #define H2DLP_IO_F64  0
@@ -86,7 +87,7 @@ typedef struct {
     int64_t n_far, n_near;      /* admissible blocks, inadmissible leaf blocks */
     int64_t coupling_entries;   /* n_far * k * k */
     int64_t near_entries;       /* sum over near blocks of |t| |s| */
-    int64_t nearsing_entries;   /* near-singular entries kept in FP64 (FP32/BF16X3 only) */
+    int64_t nearsing_entries;   /* near-singular entries kept in FP64 (all but FP64) */
     int64_t bytes_coupling, bytes_near, bytes_bases, bytes_transfer, bytes_other;
     int64_t bytes_resident;     /* all device memory held by the handle */
     int64_t workspace_bytes;    /* per concurrent apply (one 16-column pass) */
@@ -153,23 +154,32 @@ int h2dlp_export_diagonal(h2dlp_handle h, double* diag);
  * bring it back: an operator evicted to make room for others returns without
  * a rebuild.  The operator does not change after the build, so the first
  * offload copies it to the host once and keeps that copy until h2dlp_free;
- * later offloads only free, reloads copy host to device.  Synchronises the
- * device.  Apply on an offloaded handle returns EINVAL.  Both are no-ops in the
- * target state.  Errors: EINVAL (plan-only handle), ENOMEM (pinned host or
- * device allocation; reload then leaves the handle offloaded), EDEVICE. */
+ * later offloads only free, reloads copy host to device.  h2dlp_offload
+ * synchronises the device; h2dlp_reload returns when the copies are done.
+ * h2dlp_reload_ex only enqueues the copies on `stream` (a hipStream_t, NULL =
+ * the default stream) and returns: every later apply, on any stream, waits for
+ * them on the device, so the caller may launch at once.  Apply on an offloaded
+ * handle returns EINVAL.  All three are no-ops in the target state.  Errors:
+ * EINVAL (plan-only handle), ENOMEM (pinned host or device allocation; reload
+ * then leaves the handle offloaded), EDEVICE. */
 int h2dlp_offload(h2dlp_handle h);
 int h2dlp_reload(h2dlp_handle h);
+int h2dlp_reload_ex(h2dlp_handle h, void* stream);
 
 void h2dlp_free(h2dlp_handle h);
 
 const char* h2dlp_last_error(void);
 
-/* Kernel timing with hipEvents recorded around every launch of the apply, on
- * the stream the launch goes to.  Kinds: 0 permute, 1 leaf forward, 2 upward
+/* Kernel timing with hipEvents recorded around the launches of the apply, on
+ * the stream each launch goes to.  Kinds: 0 permute, 1 leaf forward, 2 upward
  * transfer, 3 coupling, 4 downward transfer, 5 leaf backward + near field +
- * diagonal.  h2dlp_profile_read synchronises the recorded events and returns
- * the summed milliseconds and launch counts per kind (n_kinds <= 6). */
+ * diagonal (+ un-permute).  `enable` is a bit mask: bit q records kind q
+ * (0 = off, H2DLP_PROFILE_ALL = every kind); record only the kinds you need,
+ * since every event pair adds a little time to the stream.
+ * h2dlp_profile_read synchronises the recorded events and returns the summed
+ * milliseconds and launch counts per kind (n_kinds <= 6). */
 #define H2DLP_NKINDS 6
+#define H2DLP_PROFILE_ALL 0x3f
 int h2dlp_profile(h2dlp_handle h, int enable);
 int h2dlp_profile_read(h2dlp_handle h, double* ms, int64_t* launches, int n_kinds, int reset);
 

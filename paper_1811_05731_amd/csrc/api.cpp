@@ -101,6 +101,7 @@ struct h2dlp_ctx {
     int device = -1;                 // -1 until device memory exists
     int m = 0, k = 0, prec = 0;
     size_t elem = 8;                 // bytes per stored value of the operator
+    size_t elem_s = 8;               // bytes per coupling entry (6 for BF16X6)
     Structure S;
     int32_t n_clusters = 0, n_leaves = 0;
     std::vector<int32_t> gid_of_pre;
@@ -135,6 +136,10 @@ struct h2dlp_ctx {
     // offload: device buffers parked in pinned host memory
     bool offloaded = false;
     struct Parked { void** field; void* host; size_t bytes; bool scratch; };
+    std::vector<bool> empty_field;   // fields() entries that hold no bytes (NULL after the build)
+    // a reload enqueued on a stream: every later use of the device buffers waits for it
+    hipEvent_t ready = nullptr;
+    bool ready_pending = false;
     std::vector<Parked> parked;
     // host-side plan
     std::vector<int32_t> child0, child1, parent;
@@ -147,7 +152,7 @@ struct h2dlp_ctx {
     int64_t off_wt = 0, off_s = 0, off_l = 0;
     h2dlp_stats st{};
     // profiling
-    bool prof = false;
+    int prof = 0;                    // bit q: record launches of kind q
     struct Rec { int kind; hipEvent_t a, b; };
     std::vector<Rec> recs;
     double prof_ms[H2DLP_NKINDS] = {0};
@@ -159,6 +164,7 @@ struct h2dlp_ctx {
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(device);
         for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+        if (ready) { (void)hipEventSynchronize(ready); (void)hipEventDestroy(ready); }
         for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
         for (auto& p : parked) if (p.host) (void)hipHostFree(p.host);
         (void)hipSetDevice(cur);
@@ -223,6 +229,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     h->k = o->order * o->order * o->order;
     h->prec = o->precision;
     h->elem = h->prec == H2DLP_FP64 ? 8 : 4;
+    h->elem_s = h->prec == H2DLP_BF16X6 ? 6 : h->elem;
     const bool fp64 = h->prec == H2DLP_FP64;
 
     std::string err = build_structure(h->S, mesh->xyz, mesh->n_nodes, mesh->tri, mesh->n_tris, o->leaf, o->eta,
@@ -276,7 +283,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     for (size_t b = 0; b < S.far.size(); ++b)
         far_by_t[h->gid_of_pre[S.far[b].first]].push_back(h->gid_of_pre[S.far[b].second]);
     int64_t off_s = 0;
-    const int kp = h->prec == H2DLP_BF16X3 ? bf16x3_cols(k) : coupling_cols(k);
+    const int kp = bf16_parts(h->prec) > 0 ? bf16s_cols(k) : coupling_cols(k);
     h->kp = kp;
     for (int32_t g = 0; g < C; ++g) {
         auto& lst = far_by_t[g];
@@ -347,7 +354,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     st.coupling_entries = int64_t(S.far.size()) * k * k;
     st.near_entries = near_entries;
     st.nearsing_entries = fp64 ? 0 : int64_t(S.ring_pos.size());
-    st.bytes_coupling = int64_t(e * size_t(st.coupling_entries));
+    st.bytes_coupling = int64_t(h->elem_s * size_t(st.coupling_entries));
     st.bytes_near = int64_t(e * size_t(near_entries));
     if (!fp64) st.bytes_near += int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8));
     st.bytes_bases = int64_t(e * size_t(2 * N * int64_t(k)));
@@ -356,7 +363,8 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
                              (h->items_fwd.size() + h->items_cpl.size() + h->items_leaf.size()) * sizeof(ItemDesc) +
                              (h->blks_fwd.size() + h->blks_cpl.size() + h->blks_leaf.size()) * sizeof(BlkDesc));
     st.workspace_bytes = int64_t(h->ws_bytes);
-    st.bytes_resident = int64_t(e * size_t(off_wt + off_s + off_l)) + st.bytes_transfer + st.bytes_other +
+    st.bytes_resident = int64_t(e * size_t(off_wt + off_l) + h->elem_s * size_t(off_s)) + st.bytes_transfer +
+                        st.bytes_other +
                         st.workspace_bytes + (fp64 ? 0 : int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8)));
     const double h2_bytes = double(st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer);
     st.compression = 1.0 - h2_bytes / (8.0 * double(N) * double(N));
@@ -382,7 +390,7 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_diag = h->alloc<double>(sizeof(double) * N, &kept);
     h->d_e = h->alloc<void>(e * size_t(C) * 3 * m * m, &kept);
     h->d_pool_wt = h->alloc<void>(e * size_t(h->off_wt), &kept);
-    h->d_pool_s = h->alloc<void>(e * size_t(h->off_s), &kept);
+    h->d_pool_s = h->alloc<void>(h->elem_s * size_t(h->off_s), &kept);
     h->d_pool_leaf = h->alloc<void>(e * size_t(h->off_l), &kept);
     h->d_items_fwd = h->upload(h->items_fwd, &kept, stream);
     h->d_blks_fwd = h->upload(h->blks_fwd, &kept, stream);
@@ -430,6 +438,8 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     check(hipStreamSynchronize(stream), "build synchronize");
     for (void* p : temp) h->release(p);
     h->d_ws = h->alloc<void>(h->ws_bytes, &kept);
+    h->empty_field.clear();
+    for (auto& f : h->fields()) h->empty_field.push_back(*f.first == nullptr);
     // host-side descriptors are no longer needed
     h->leaves.clear(); h->leaves.shrink_to_fit();
     h->vleaves.clear(); h->vleaves.shrink_to_fit();
@@ -441,13 +451,13 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
 
 h2dlp_ctx* as_ctx(h2dlp_handle h) { return reinterpret_cast<h2dlp_ctx*>(h); }
 
-void rec_begin(h2dlp_ctx* h, hipStream_t s, hipEvent_t* a) {
-    if (!h->prof) return;
+void rec_begin(h2dlp_ctx* h, hipStream_t s, int kind, hipEvent_t* a) {
+    if (!(h->prof >> kind & 1)) return;
     check(hipEventCreate(a), "event");
     check(hipEventRecord(*a, s), "event record");
 }
 void rec_end(h2dlp_ctx* h, hipStream_t s, int kind, hipEvent_t a) {
-    if (!h->prof) return;
+    if (!(h->prof >> kind & 1)) return;
     hipEvent_t b;
     check(hipEventCreate(&b), "event");
     check(hipEventRecord(b, s), "event record");
@@ -455,14 +465,25 @@ void rec_end(h2dlp_ctx* h, hipStream_t s, int kind, hipEvent_t a) {
 }
 
 int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStream_t s, void* ws) {
-    // every buffer the kernels read must exist (an offloaded operator has none)
-    for (auto& f : h->fields()) {
-        const bool optional = f.first == (void**)&h->d_ns_off || f.first == (void**)&h->d_ns_pos ||
-                              f.first == (void**)&h->d_ns_val;
-        if (*f.first == nullptr && !(optional && h->prec == H2DLP_FP64))
-            return fail(H2DLP_EINVAL, "operator buffers are not on the device");
+    // every buffer the kernels read must exist (an offloaded operator has none);
+    // buffers that were empty at the build (no far blocks, FP64 near-singular
+    // arrays) stay NULL
+    {
+        const auto fs = h->fields();
+        for (size_t q = 0; q < fs.size(); ++q)
+            if (*fs[q].first == nullptr && !h->empty_field[q])
+                return fail(H2DLP_EINVAL, "operator buffers are not on the device");
     }
     if (ws == nullptr) return fail(H2DLP_EINVAL, "no workspace");
+    if (h->ready_pending) {        // copies of an asynchronous reload may still be in flight
+        const hipError_t q = hipEventQuery(h->ready);
+        if (q == hipSuccess) {
+            h->ready_pending = false;
+        } else {
+            if (q == hipErrorNotReady) (void)hipGetLastError();   // not an error: do not leave it behind
+            check(hipStreamWaitEvent(s, h->ready, 0), "waiting for the reload");
+        }
+    }
     const int64_t N = h->S.n_nodes;
     const int m = h->m, k = h->k, prec = h->prec;
     char* base = static_cast<char*>(ws);
@@ -477,36 +498,36 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         const void* u1p = static_cast<const char*>(u1) + io_elem * size_t(c0) * N;
         void* u2p = static_cast<char*>(u2) + io_elem * size_t(c0) * N;
         hipEvent_t ev = nullptr;
-        rec_begin(h, s, &ev);
+        rec_begin(h, s, 0, &ev);
         check(launch_permute(u1p, io, N, nr, h->d_iperm, x, h->ws_x64 ? x64 : nullptr, prec, s), "permute");
         rec_end(h, s, 0, ev);
 
         ProductArgs fwd{h->d_items_fwd, h->n_items_fwd, (k + 15) / 16, h->d_blks_fwd, h->d_pool_wt, x, nullptr, xh};
-        rec_begin(h, s, &ev);
+        rec_begin(h, s, 1, &ev);
         check(launch_product_store(fwd, prec, true, s), "leaf forward");
         rec_end(h, s, 1, ev);
 
         for (int l = h->S.depth - 1; l >= 0; --l) {
-            rec_begin(h, s, &ev);
+            rec_begin(h, s, 2, &ev);
             check(launch_upward(h->level_off[l], h->level_off[l + 1], h->d_child0, h->d_child1, h->d_e, xh, m, prec, s),
                   "upward");
             rec_end(h, s, 2, ev);
         }
 
         ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
-        rec_begin(h, s, &ev);
+        rec_begin(h, s, 3, &ev);
         check(launch_coupling(cpl, k, prec, s), "coupling");
         rec_end(h, s, 3, ev);
 
         for (int l = 1; l <= h->S.depth; ++l) {
-            rec_begin(h, s, &ev);
+            rec_begin(h, s, 4, &ev);
             check(launch_downward(h->level_off[l], h->level_off[l + 1], h->d_parent, h->d_e, yh, m, prec, s), "downward");
             rec_end(h, s, 4, ev);
         }
 
         ProductArgs leaf{h->d_items_leaf, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
         LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
-        rec_begin(h, s, &ev);
+        rec_begin(h, s, 5, &ev);
         check(launch_product_leaf(leaf, epi, prec, s), "leaf output");
         check(launch_unpermute(y64, io, N, nr, h->d_iperm, u2p, s), "unpermute");
         rec_end(h, s, 5, ev);
@@ -541,9 +562,10 @@ static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_hand
     if (o->leaf < 1 || o->leaf > 64) return fail(H2DLP_EINVAL, "leaf must be in [1, 64]");
     if (!(o->eta > 0.0) || !std::isfinite(o->eta)) return fail(H2DLP_EINVAL, "eta must be positive");
     if (!(o->alpha >= 0.0 && o->alpha <= 1.0)) return fail(H2DLP_EINVAL, "alpha must be in [0, 1]");
-    if (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32 && o->precision != H2DLP_BF16X3)
+    if (o->precision < H2DLP_FP64 || o->precision > H2DLP_BF16X6)
         return fail(H2DLP_EINVAL, "unknown precision");
-    if (o->precision == H2DLP_BF16X3 && o->order > 5) return fail(H2DLP_ENOTSUP, "BF16X3 needs order <= 5 (k <= 128)");
+    if ((o->precision == H2DLP_BF16X3 || o->precision == H2DLP_BF16X6) && o->order > 5)
+        return fail(H2DLP_ENOTSUP, "BF16X3 and BF16X6 need order <= 5 (k <= 128)");
     return H2DLP_OK;
 }
 
@@ -683,6 +705,7 @@ int h2dlp_export_diagonal(h2dlp_handle hh, double* diag) {
     if (h->offloaded) return fail(H2DLP_EINVAL, "operator is offloaded: call h2dlp_reload first");
     std::vector<double> d(h->S.n_nodes);
     if (hipSetDevice(h->device) != hipSuccess ||
+        (h->ready_pending && hipEventSynchronize(h->ready) != hipSuccess) ||
         hipMemcpy(d.data(), h->d_diag, sizeof(double) * d.size(), hipMemcpyDeviceToHost) != hipSuccess)
         return fail(H2DLP_EDEVICE, "copying the diagonal failed");
     for (int64_t p = 0; p < h->S.n_nodes; ++p) diag[h->S.perm[p]] = d[p];
@@ -698,6 +721,7 @@ int h2dlp_offload(h2dlp_handle hh) {
     (void)hipGetDevice(&cur);
     if (hipSetDevice(h->device) != hipSuccess || hipDeviceSynchronize() != hipSuccess)
         return fail(H2DLP_EDEVICE, "synchronising the device before offload failed");
+    h->ready_pending = false;
     // the operator never changes after the build: the first offload keeps a
     // pinned host copy for good, later offloads only free the device memory
     if (h->parked.empty()) {
@@ -737,13 +761,19 @@ int h2dlp_offload(h2dlp_handle hh) {
     return H2DLP_OK;
 }
 
-int h2dlp_reload(h2dlp_handle hh) {
+int h2dlp_reload_ex(h2dlp_handle hh, void* stream) {
     h2dlp_ctx* h = as_ctx(hh);
     if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
     if (!h->offloaded) return H2DLP_OK;
     int cur = 0;
     (void)hipGetDevice(&cur);
     if (hipSetDevice(h->device) != hipSuccess) return fail(H2DLP_EDEVICE, "hipSetDevice failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!h->ready && hipEventCreateWithFlags(&h->ready, hipEventDisableTiming) != hipSuccess) {
+        h->ready = nullptr;
+        (void)hipSetDevice(cur);
+        return fail(H2DLP_EDEVICE, "creating the reload event failed");
+    }
     int rc = H2DLP_OK;
     size_t done = 0;
     try {
@@ -751,7 +781,7 @@ int h2dlp_reload(h2dlp_handle hh) {
             auto& p = h->parked[done];
             void* d = h->alloc<void>(p.bytes, nullptr);
             *p.field = d;
-            if (!p.scratch && hipMemcpy(d, p.host, p.bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            if (!p.scratch && hipMemcpyAsync(d, p.host, p.bytes, hipMemcpyHostToDevice, s) != hipSuccess) {
                 ++done;
                 rc = fail(H2DLP_EDEVICE, "copy to device failed");
                 break;
@@ -760,7 +790,10 @@ int h2dlp_reload(h2dlp_handle hh) {
     } catch (const std::bad_alloc&) {
         rc = fail(H2DLP_ENOMEM, "device allocation failed during reload");
     }
-    if (rc != H2DLP_OK) {           // back to the offloaded state
+    if (rc == H2DLP_OK && hipEventRecord(h->ready, s) != hipSuccess)
+        rc = fail(H2DLP_EDEVICE, "recording the reload event failed");
+    if (rc != H2DLP_OK) {           // back to the offloaded state once enqueued copies are done
+        (void)hipStreamSynchronize(s);
         for (size_t q = 0; q < done && q < h->parked.size(); ++q) {
             h->release(*h->parked[q].field);
             *h->parked[q].field = nullptr;
@@ -768,8 +801,20 @@ int h2dlp_reload(h2dlp_handle hh) {
         (void)hipSetDevice(cur);
         return rc;
     }
+    h->ready_pending = true;
     h->offloaded = false;
     (void)hipSetDevice(cur);
+    return H2DLP_OK;
+}
+
+int h2dlp_reload(h2dlp_handle hh) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    if (!h->offloaded) return H2DLP_OK;
+    int rc = h2dlp_reload_ex(hh, nullptr);
+    if (rc != H2DLP_OK) return rc;
+    if (hipEventSynchronize(h->ready) != hipSuccess) return fail(H2DLP_EDEVICE, "waiting for the reload failed");
+    h->ready_pending = false;
     return H2DLP_OK;
 }
 
@@ -780,7 +825,7 @@ const char* h2dlp_last_error(void) { return g_last_error.c_str(); }
 int h2dlp_profile(h2dlp_handle hh, int enable) {
     h2dlp_ctx* h = as_ctx(hh);
     if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
-    h->prof = enable != 0;
+    h->prof = enable & ((1 << H2DLP_NKINDS) - 1);
     return H2DLP_OK;
 }
 

@@ -361,17 +361,19 @@ __global__ void __launch_bounds__(kThreads) k_coupling(ProductArgs a, int kvalid
         }
 }
 
-// BF16x3 coupling products (k <= 128): S_ts = S_hi + S_lo pre-split at build
-// time (layout.h, bf16x3 layout), xhat = x_hi + x_lo split here, and
-// S xhat ~ S_hi x_hi + S_hi x_lo + S_lo x_hi on the 16x16x32 bf16 MFMA with FP32
-// accumulation.  A k-step covers 32 columns: lane group g, slot j holds column
-// 32 ks + 8 g + j in both operands, so the sum over the MFMA's K dimension is the
-// sum over those columns whatever order the unit uses inside.
+// Split-bfloat16 coupling products (k <= 128).  S_ts is pre-split at build time
+// into P bfloat16 terms (layout.h, split layout); xhat is split here into P
+// terms the same way.  P = 2 (BF16X3): S xhat ~ S1 x1 + S1 x2 + S2 x1.  P = 3
+// (BF16X6): S1 x1 + S1 x2 + S2 x1 + S1 x3 + S2 x2 + S3 x1, every product of
+// combined order <= 3.  All on the 16x16x32 bf16 MFMA with FP32 accumulation.
+// A k-step covers 32 columns: lane group g, slot j holds column 32 ks + 8 g + j
+// in both operands, so the sum over the MFMA's K dimension is the sum over
+// those columns whatever order the unit uses inside.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-template <int RT>
-__global__ void __launch_bounds__(kThreads) k_coupling_bf16x3(ProductArgs a, int kvalid) {
+template <int RT, int P>
+__global__ void __launch_bounds__(kThreads) k_coupling_bf16s(ProductArgs a, int kvalid) {
     constexpr int KS = (RT + 1) / 2;          // 32-column k-steps per block
     extern __shared__ unsigned char smem_raw[];
     float* red = reinterpret_cast<float*>(smem_raw);
@@ -388,9 +390,9 @@ __global__ void __launch_bounds__(kThreads) k_coupling_bf16x3(ProductArgs a, int
     for (int r = 0; r < RT; ++r) {
         const unsigned rv = unsigned(M - 16 * r < 16 ? M - 16 * r : 16);
         ok[r] = i < rv;
-        loff[r] = ok[r] ? 2048u * r + 32u * (g * rv + i) : 0u;   // bytes
+        loff[r] = ok[r] ? 1024u * P * r + 16u * P * (g * rv + i) : 0u;   // bytes
     }
-    const unsigned kbytes = 128u * unsigned(M);                   // one k-step: M rows x 32 (hi, lo) pairs
+    const unsigned kbytes = 64u * P * unsigned(M);                       // one k-step: M rows x 32 entries
     const unsigned char* pool = static_cast<const unsigned char*>(a.pool);
     const float* xh = static_cast<const float*>(a.x0);
     const int first = it.blk_begin + w;
@@ -400,13 +402,13 @@ __global__ void __launch_bounds__(kThreads) k_coupling_bf16x3(ProductArgs a, int
     f32x4 acc[RT];
 #pragma unroll
     for (int r = 0; r < RT; ++r) acc[r] = f32x4{0, 0, 0, 0};
-    u32x4 h0[RT], l0[RT], h1[RT], l1[RT];
+    u32x4 s0[P][RT], s1[P][RT];
     float x0v[8], x1v[8];
 
-    auto load = [&](int n, u32x4* hv, u32x4* lv, float* xv) {
+    auto load = [&](int n, u32x4 (*sv)[RT], float* xv) {
         const int j = n / KS, ks = n - j * KS;
         const BlkDesc d = a.blks[first + kWaves * j];
-        const unsigned char* Ab = pool + int64_t(d.a_off) * 4 + kbytes * ks;
+        const unsigned char* Ab = pool + int64_t(d.a_off) * (2 * P) + kbytes * ks;
         const float* X = xh + int64_t(d.src) * RHS_TILE;
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
@@ -415,38 +417,45 @@ __global__ void __launch_bounds__(kThreads) k_coupling_bf16x3(ProductArgs a, int
             xv[jj] = row < kvalid ? v : 0.f;
         }
 #pragma unroll
-        for (int r = 0; r < RT; ++r) {
-            hv[r] = ld<u32x4>(Ab, loff[r]);
-            lv[r] = ld<u32x4>(Ab, loff[r] + 16u);
-        }
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int q = 0; q < P; ++q) sv[q][r] = ld<u32x4>(Ab, loff[r] + 16u * q);
     };
-    auto compute = [&](const u32x4* hv, const u32x4* lv, const float* xv) {
-        bf16x8 bh, bl;
+    auto compute = [&](u32x4 (*sv)[RT], const float* xv) {
+        bf16x8 bx[P];
 #pragma unroll
         for (int jj = 0; jj < 8; ++jj) {
-            const __bf16 hi = __bf16(xv[jj]);
-            bh[jj] = hi;
-            bl[jj] = __bf16(xv[jj] - float(hi));
+            float rem = xv[jj];
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const __bf16 t = __bf16(rem);
+                bx[q][jj] = t;
+                rem -= float(t);                   // exact: what the earlier terms leave
+            }
         }
         const u32x4 zero = {0u, 0u, 0u, 0u};
 #pragma unroll
         for (int r = 0; r < RT; ++r) {
-            const bf16x8 ah = __builtin_bit_cast(bf16x8, ok[r] ? hv[r] : zero);
-            const bf16x8 al = __builtin_bit_cast(bf16x8, ok[r] ? lv[r] : zero);
-            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[r], 0, 0, 0);
-            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[r], 0, 0, 0);
-            acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[r], 0, 0, 0);
+            bf16x8 as[P];
+#pragma unroll
+            for (int q = 0; q < P; ++q) as[q] = __builtin_bit_cast(bf16x8, ok[r] ? sv[q][r] : zero);
+            // products S_a x_b with a + b <= P - 1 (0-based term indices), highest order first
+#pragma unroll
+            for (int o = P - 1; o >= 0; --o)
+#pragma unroll
+                for (int q = 0; q <= o; ++q)
+                    acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as[q], bx[o - q], acc[r], 0, 0, 0);
         }
     };
     int n = 0;
-    if (units > 0) load(0, h0, l0, x0v);
+    if (units > 0) load(0, s0, x0v);
     for (; n + 2 <= units; n += 2) {
-        load(n + 1, h1, l1, x1v);
-        compute(h0, l0, x0v);
-        if (n + 2 < units) load(n + 2, h0, l0, x0v);
-        compute(h1, l1, x1v);
+        load(n + 1, s1, x1v);
+        compute(s0, x0v);
+        if (n + 2 < units) load(n + 2, s0, x0v);
+        compute(s1, x1v);
     }
-    if (n < units) compute(h0, l0, x0v);
+    if (n < units) compute(s0, x0v);
 
     if (w > 0) {
         float* slot = red + (w - 1) * RT * 256;
@@ -708,17 +717,25 @@ hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows
 
 hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st) {
     const int rt = (k + 15) / 16;
-    if (prec == P_BF16X3) {
+    if (prec == P_BF16X3 || prec == P_BF16X6) {
         const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
         if (grid == 0) return hipSuccess;
         const size_t lds = size_t(kWaves - 1) * rt * 256 * sizeof(float);
+#define H2DLP_SPLIT_CASE(R)                                                                                  \
+    case R:                                                                                                  \
+        if (prec == P_BF16X3)                                                                                \
+            hipLaunchKernelGGL((k_coupling_bf16s<R, 2>), dim3(grid), dim3(kThreads), lds, st, a, k);         \
+        else                                                                                                 \
+            hipLaunchKernelGGL((k_coupling_bf16s<R, 3>), dim3(grid), dim3(kThreads), lds, st, a, k);         \
+        break;
         switch (rt) {
-            case 1: hipLaunchKernelGGL((k_coupling_bf16x3<1>), dim3(grid), dim3(kThreads), lds, st, a, k); break;
-            case 2: hipLaunchKernelGGL((k_coupling_bf16x3<2>), dim3(grid), dim3(kThreads), lds, st, a, k); break;
-            case 4: hipLaunchKernelGGL((k_coupling_bf16x3<4>), dim3(grid), dim3(kThreads), lds, st, a, k); break;
-            case 8: hipLaunchKernelGGL((k_coupling_bf16x3<8>), dim3(grid), dim3(kThreads), lds, st, a, k); break;
+            H2DLP_SPLIT_CASE(1)
+            H2DLP_SPLIT_CASE(2)
+            H2DLP_SPLIT_CASE(4)
+            H2DLP_SPLIT_CASE(8)
             default: return hipErrorInvalidValue;
         }
+#undef H2DLP_SPLIT_CASE
         return hipGetLastError();
     }
     if (rt > 8 || (rt & (rt - 1)) != 0) {   // large orders: generic product (blocks stored k x k)

@@ -239,7 +239,9 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_transfer(const double* 
 
 // Coupling matrix of an admissible block: S(nu, mu) = 1/(4 pi |eta^t_nu - eta^s_mu|),
 // stored k x kp with zero columns mu >= k.
-// BF16X3 stores each entry as (hi, lo) bfloat16, hi = bf16(S), lo = bf16(S - hi).
+// BF16X3 stores each entry as (hi, lo) bfloat16, hi = bf16(S), lo = bf16(S - hi);
+// BF16X6 as (hi, mid, lo), each term the bfloat16 rounding of what the earlier
+// terms leave of S (remainders taken in FP64).
 __global__ void __launch_bounds__(kBuildThreads) k_build_coupling(const double* boxes, int m, int kp,
                                                                   const FarDesc* far, int prec, void* pool) {
     __shared__ double pt[3][8], ps[3][8];
@@ -257,14 +259,16 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_coupling(const double* 
             const double dz = pt[2][nu / (m * m)] - ps[2][mu / (m * m)];
             v = 1.0 / (4.0 * kPi * sqrt(dx * dx + dy * dy + dz * dz));
         }
-        if (prec == P_BF16X3) {
-            // a_off counts 4-byte entries; the pair (hi, lo) of entry (nu, mu) sits in the bf16x3 layout
-            const float f = float(v);
-            const __bf16 hi = __bf16(f);
-            const __bf16 lo = __bf16(f - float(hi));
-            __bf16* base = static_cast<__bf16*>(pool) + 2 * F.a_off;
-            base[bf16x3_offset(k, nu, mu, 0)] = hi;
-            base[bf16x3_offset(k, nu, mu, 1)] = lo;
+        const int P = bf16_parts(prec);
+        if (P > 0) {
+            // a_off counts entries of P bfloat16 terms each, placed by the split layout
+            __bf16* base = static_cast<__bf16*>(pool) + int64_t(P) * F.a_off;
+            double rem = v;
+            for (int q = 0; q < P; ++q) {
+                const __bf16 t = __bf16(float(rem));
+                base[bf16s_offset(k, nu, mu, q, P)] = t;
+                rem -= double(float(t));
+            }
         } else {
             put_prec(pool, F.a_off + a_offset(k, kp, nu, mu), v, prec);
         }

@@ -9,7 +9,9 @@
 
 namespace h2dlp {
 
-enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2 };
+enum Prec { P_FP64 = 0, P_FP32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
+// bfloat16 terms per coupling entry: 2 (BF16X3), 3 (BF16X6), 0 otherwise
+H2DLP_HD inline int bf16_parts(int prec) { return prec == P_BF16X3 ? 2 : (prec == P_BF16X6 ? 3 : 0); }
 
 // ---------------------------------------------------------------- build (FP64 arithmetic)
 

@@ -50,18 +50,19 @@ H2DLP_HD inline int64_t a_offset(int M, int K, int row, int col) {
     return int64_t(16) * M * G + int64_t(4) * M * ks + 16 * rt * kv + kk * rv + i;
 }
 
-// BF16x3 coupling blocks (k <= 128): M x KP entries, KP = 32 ceil(k / 32)
-// (zero columns past k), each entry a (hi, lo) pair of bfloat16.  Columns come
-// in k-steps of 32; chunk (ks, rt) of row tile rt starts at bf16 index
-// 64 M ks + 1024 rt and lane (i, g) of the 16x16x32 MFMA owns 16 contiguous
-// values at (g rv + i) 16: hi of columns 32 ks + 8 g + j (j < 8), then lo.
-H2DLP_HD inline int64_t bf16x3_offset(int M, int row, int col, int part) {
+// Split-bfloat16 coupling blocks (k <= 128): M x KP entries, KP = 32 ceil(k / 32)
+// (zero columns past k), each entry a sum of P bfloat16 terms (P = 2: hi, lo;
+// P = 3: hi, mid, lo).  Columns come in k-steps of 32; chunk (ks, rt) of row
+// tile rt starts at bf16 index 32 P M ks + 512 P rt and lane (i, g) of the
+// 16x16x32 MFMA owns 8 P contiguous values at (g rv + i) 8 P: term 0 of
+// columns 32 ks + 8 g + j (j < 8), then term 1, ...
+H2DLP_HD inline int64_t bf16s_offset(int M, int row, int col, int part, int P) {
     const int rt = row >> 4, i = row & 15;
     const int rv = (M - 16 * rt) < 16 ? (M - 16 * rt) : 16;
     const int ks = col >> 5, g = (col & 31) >> 3, j = col & 7;
-    return int64_t(64) * M * ks + 1024 * rt + (g * rv + i) * 16 + 8 * part + j;
+    return int64_t(32 * P) * M * ks + 512 * P * rt + (g * rv + i) * 8 * P + 8 * part + j;
 }
-H2DLP_HD inline int bf16x3_cols(int k) { return 32 * ((k + 31) / 32); }
+H2DLP_HD inline int bf16s_cols(int k) { return 32 * ((k + 31) / 32); }
 
 // One output tile of a grouped block product: rows [out_row, out_row + m) of
 // the output array receive sum over blocks b in [blk_begin, blk_end) of A_b X_b.

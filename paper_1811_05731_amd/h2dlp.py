@@ -17,11 +17,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libh2dlp.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
-FP64, FP32, BF16X3 = 0, 1, 2
+FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 IO_F64, IO_F32 = 0, 1
 NKINDS = 6
 KIND_NAMES = ("permute", "leaf_forward", "upward", "coupling", "downward", "leaf_output")
-PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3}
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 
 
 class H2dlpError(RuntimeError):
@@ -57,7 +57,7 @@ class _Stats(ctypes.Structure):
 
 EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
             "h2dlp_bytes", "h2dlp_info", "h2dlp_export_structure", "h2dlp_export_diagonal", "h2dlp_offload",
-            "h2dlp_reload", "h2dlp_free",
+            "h2dlp_reload", "h2dlp_reload_ex", "h2dlp_free",
             "h2dlp_last_error", "h2dlp_profile", "h2dlp_profile_read")
 
 
@@ -94,6 +94,8 @@ def _load():
     lib.h2dlp_offload.restype = I
     lib.h2dlp_reload.argtypes = [V]
     lib.h2dlp_reload.restype = I
+    lib.h2dlp_reload_ex.argtypes = [V, V]
+    lib.h2dlp_reload_ex.restype = I
     lib.h2dlp_free.argtypes = [V]
     lib.h2dlp_free.restype = None
     lib.h2dlp_last_error.argtypes = []
@@ -237,12 +239,27 @@ class Operator:
         """Park the operator in pinned host memory and free its HBM."""
         _check(_lib.h2dlp_offload(self._h))
 
-    def reload(self):
-        """Bring an offloaded operator back to the device."""
-        _check(_lib.h2dlp_reload(self._h))
+    def reload(self, stream=None):
+        """Bring an offloaded operator back to the device.
 
-    def profile(self, enable: bool = True):
-        _check(_lib.h2dlp_profile(self._h, int(enable)))
+        Without a stream this returns when the copies are done; with a torch
+        stream the copies are only enqueued there, and every later apply waits
+        for them on the device."""
+        if stream is None:
+            _check(_lib.h2dlp_reload(self._h))
+        else:
+            _check(_lib.h2dlp_reload_ex(self._h, ctypes.c_void_p(stream.cuda_stream)))
+
+    def profile(self, enable=True):
+        """Record per-kernel HIP events: True = every kind, False = off, or an
+        iterable of kind names (KIND_NAMES) to record only those."""
+        if enable is True or enable is False:
+            mask = (1 << NKINDS) - 1 if enable else 0
+        else:
+            mask = 0
+            for name in enable:
+                mask |= 1 << KIND_NAMES.index(name)
+        _check(_lib.h2dlp_profile(self._h, mask))
 
     def profile_read(self, reset: bool = True) -> dict:
         ms = (ctypes.c_double * NKINDS)()

@@ -8,7 +8,10 @@ runs up to `n_slots` applies at once on their own streams with their own
 workspaces, and admits new work whenever a slot frees up -- requests that
 arrive while others are on the GPU join the next batch of their mesh.
 Operators that do not fit are made room for by parking idle ones in pinned
-host memory (least recently used first) and reloading them later.
+host memory and reloading them later; the victim is the smallest idle operator
+whose bytes make enough room (reload time grows with size), least recently
+used first among equals.  A reload is enqueued on the stream of the batch that
+needs it, so the loop keeps serving resident meshes while it runs.
 
 The scheduler is independent of the GPU: `Backend` is the interface it drives.
 `GpuBackend` implements it on the HIP library; tests drive the same scheduler
@@ -73,14 +76,17 @@ class Backend:
     def offload(self, op) -> None:
         raise NotImplementedError
 
-    def reload(self, op) -> None:
+    def reload(self, op, slot=None) -> None:        # may be asynchronous on the slot's stream
         raise NotImplementedError
 
     def free(self, op) -> None:
         raise NotImplementedError
 
-    def make_slots(self, n: int, workspace_bytes: int) -> list:
+    def make_slots(self, n: int, workspace_bytes: int, max_values: int = 0) -> list:
         raise NotImplementedError
+
+    def staging_bytes(self, max_values: int) -> int:            # device bytes per slot beyond the workspace
+        return 0
 
     def launch(self, slot, op, u1: np.ndarray) -> Any:       # -> ticket
         raise NotImplementedError
@@ -115,31 +121,48 @@ class GpuBackend(Backend):
     def offload(self, op):
         op.offload()
 
-    def reload(self, op):
-        op.reload()
+    def reload(self, op, slot=None):
+        op.reload(stream=None if slot is None else slot["stream"])
 
     def free(self, op):
         op.close()
 
-    def make_slots(self, n, workspace_bytes):
+    def staging_bytes(self, max_values):
+        return 2 * 8 * max(1, max_values)
+
+    def make_slots(self, n, workspace_bytes, max_values=0):
+        """Per slot: a stream, a workspace, and pinned host and device staging
+        for `max_values` input and output values (allocated once)."""
         t = self.torch
-        return [{"stream": t.cuda.Stream(device=self.device),
-                 "ws": t.empty(max(1, workspace_bytes), dtype=t.uint8, device=self.device)} for _ in range(n)]
+        slots = []
+        for _ in range(n):
+            v = max(1, max_values)
+            slots.append({"stream": t.cuda.Stream(device=self.device),
+                          "ws": t.empty(max(1, workspace_bytes), dtype=t.uint8, device=self.device),
+                          "h_in": t.empty(v, dtype=t.float64, pin_memory=True),
+                          "h_out": t.empty(v, dtype=t.float64, pin_memory=True),
+                          "d_in": t.empty(v, dtype=t.float64, device=self.device),
+                          "d_out": t.empty(v, dtype=t.float64, device=self.device)})
+        return slots
 
     def launch(self, slot, op, u1):
         t = self.torch
         s = slot["stream"]
-        host = t.from_numpy(np.ascontiguousarray(u1, dtype=np.float64)).pin_memory()
+        r, n = u1.shape
+        if r * n > slot["h_in"].numel():
+            raise ValueError("batch larger than the slot's staging buffers")
+        h_in = slot["h_in"][:r * n].view(r, n)
+        h_in.numpy()[...] = u1
+        d1 = slot["d_in"][:r * n].view(r, n)
+        d2 = slot["d_out"][:r * n].view(r, n)
+        h_out = slot["h_out"][:r * n].view(r, n)
         with t.cuda.stream(s):
-            d1 = t.empty(host.shape, dtype=t.float64, device=self.device)
-            d1.copy_(host, non_blocking=True)
-            d2 = t.empty_like(d1)
+            d1.copy_(h_in, non_blocking=True)
             op.apply(d1, d2, stream=s, workspace=slot["ws"])
-            out = t.empty(host.shape, dtype=t.float64, pin_memory=True)
-            out.copy_(d2, non_blocking=True)
+            h_out.copy_(d2, non_blocking=True)
             ev = t.cuda.Event()
             ev.record(s)
-        return (ev, out, host, d1, d2)
+        return (ev, h_out)
 
     def poll(self, ticket):
         return ticket[0].query()
@@ -198,8 +221,16 @@ class Server:
         resident, ws = self.backend.plan_bytes(spec)
         self.meshes[spec.mesh_id] = _Mesh(spec, int(resident), int(ws))
 
+    def _max_values(self) -> int:
+        return self.max_batch_rhs * max((m.spec.n_nodes for m in self.meshes.values()), default=1)
+
     def _slot_bytes(self) -> int:
-        return self.n_slots * max((m.workspace_bytes for m in self.meshes.values()), default=0)
+        ws = max((m.workspace_bytes for m in self.meshes.values()), default=0)
+        return self.n_slots * (ws + self.backend.staging_bytes(self._max_values()))
+
+    def fixed_bytes(self) -> int:
+        """Device bytes the slots hold whatever is resident (workspaces and staging)."""
+        return self._slot_bytes()
 
     def _used(self) -> int:
         return self._slot_bytes() + sum(m.resident_bytes for m in self.meshes.values() if m.on_device)
@@ -210,15 +241,26 @@ class Server:
     def _patience(self, m: _Mesh) -> float:
         return self.aging + 2.0 * m.resident_bytes / self.reload_bytes_per_s
 
-    def _make_resident(self, m: _Mesh) -> bool:
-        """Evict idle operators (least recently used first) until m fits; then build or reload it."""
+    def _victim(self, need: int) -> Optional[_Mesh]:
+        """The idle operator to offload next when `need` more bytes are wanted:
+        the smallest one that makes enough room on its own, else the largest
+        (fewest evictions); least recently used first among equal sizes."""
+        idle = [x for x in self.meshes.values() if x.on_device and x.inflight == 0]
+        if not idle:
+            return None
+        enough = [x for x in idle if x.resident_bytes >= need]
+        if enough:
+            return min(enough, key=lambda x: (x.resident_bytes, x.last_used))
+        return max(idle, key=lambda x: (x.resident_bytes, -x.last_used))
+
+    def _make_resident(self, m: _Mesh, slot=None) -> bool:
+        """Offload idle operators until m fits; then build m, or reload it on the slot's stream."""
         if m.on_device:
             return True
         while self._used() + m.resident_bytes > self.budget:
-            idle = [x for x in self.meshes.values() if x.on_device and x.inflight == 0 and x is not m]
-            if not idle:
+            victim = self._victim(self._used() + m.resident_bytes - self.budget)
+            if victim is None:
                 return False
-            victim = min(idle, key=lambda x: x.last_used)
             self.backend.offload(victim.op)
             victim.on_device = False
             victim.offloads += 1
@@ -226,7 +268,7 @@ class Server:
             m.op = self.backend.build(m.spec)
             m.builds += 1
         else:
-            self.backend.reload(m.op)
+            self.backend.reload(m.op, slot)
             m.reloads += 1
         m.on_device = True
         return True
@@ -251,6 +293,8 @@ class Server:
             return self._reject(req, f"unknown mesh {req.mesh_id!r}")
         if u.ndim != 2 or u.shape[1] != m.spec.n_nodes or u.shape[0] < 1:
             return self._reject(req, f"u1 must have shape (r, {m.spec.n_nodes})")
+        if u.shape[0] > self.max_batch_rhs:
+            return self._reject(req, f"more than max_batch_rhs = {self.max_batch_rhs} columns")
         if not np.all(np.isfinite(u)):
             return self._reject(req, "u1 has non-finite values")
         if not self._fits(m):
@@ -270,8 +314,9 @@ class Server:
                                         m.queue[0].arrival))
             started = False
             for m in waiting:
+                slot = self.free_slots[-1]
                 try:
-                    ok = self._make_resident(m)
+                    ok = self._make_resident(m, slot)
                 except Exception as e:  # build / reload failure: fail this mesh's queue
                     while m.queue:
                         self._reject(m.queue.popleft(), f"could not make operator resident: {e}")
@@ -279,12 +324,12 @@ class Server:
                 if not ok:
                     continue
                 batch, cols = [], 0
-                while m.queue and (not batch or cols + m.queue[0].nrhs <= self.max_batch_rhs):
+                while m.queue and cols + m.queue[0].nrhs <= self.max_batch_rhs:
                     r = m.queue.popleft()
                     batch.append(r)
                     cols += r.nrhs
                 u = np.concatenate([np.atleast_2d(r.u1) for r in batch], axis=0)
-                slot = self.free_slots.pop()
+                self.free_slots.pop()
                 try:
                     ticket = self.backend.launch(slot, m.op, u)
                 except Exception as e:
@@ -328,7 +373,7 @@ class Server:
         """Serve `requests` (Request objects with arrival times relative to the start)."""
         if self.slots is None:
             self.slots = self.backend.make_slots(self.n_slots, max((m.workspace_bytes for m in self.meshes.values()),
-                                                                   default=1))
+                                                                   default=1), self._max_values())
             self.free_slots = list(self.slots)
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         self.t0 = self.clock()

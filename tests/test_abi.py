@@ -45,6 +45,9 @@ def test_argument_errors():
     assert _plan_rc(xyz, tri, eta=0.0) == h2dlp.EINVAL
     assert _plan_rc(xyz, tri, eta=float("nan")) == h2dlp.EINVAL
     assert _plan_rc(xyz, tri, alpha=-0.1) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, order=6, precision="bf16x3") == h2dlp.ENOTSUP
+    assert _plan_rc(xyz, tri, order=6, precision="bf16x6") == h2dlp.ENOTSUP
+    assert _plan_rc(xyz, tri, order=5, precision="bf16x6") == 0
     lib = h2dlp.library()
     out = ctypes.c_void_p()
     opt = h2dlp._Options()
@@ -110,6 +113,11 @@ def test_plan_sizes():
     s32 = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, precision="fp32").stats
     assert s32.bytes_coupling == 4 * s.coupling_entries
     assert 10 * xyz.shape[0] < s32.nearsing_entries < 25 * xyz.shape[0]   # the 2-ring, ~18 per node
+    s3 = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, precision="bf16x3").stats
+    s6 = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, precision="bf16x6").stats
+    assert s3.bytes_coupling == 4 * s.coupling_entries and s6.bytes_coupling == 6 * s.coupling_entries
+    assert s6.bytes_resident - s3.bytes_resident == 2 * s.coupling_entries   # k = 64: no padding columns
+    assert s6.bytes_near == s32.bytes_near and s6.bytes_bases == s32.bytes_bases
     r, w = h2dlp.plan(xyz, tri).bytes()
     assert w > 0 and r > w
 

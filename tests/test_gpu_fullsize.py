@@ -3,15 +3,18 @@
 * Sampled parity: 16 right-hand sides that are unit vectors at seeded nodes.
   The oracle then needs only the clusters, blocks and bases those nodes touch,
   yet every output entry (all N rows of each column) is compared.
-* Dense rows: at 163842 nodes, a seeded sample of rows of the exact dense
-  matrix (Section 3) bounds the H2 approximation error.
+* Dense rows: at 163842 nodes, 1000 seeded rows of the exact dense matrix
+  (Section 3), stored by tests/golden/make_dense_rows.py, bound the H2
+  approximation error.
 * Physics at 655362 nodes: u1 = z gives u2 ~ -2z/3 and the sphere's energy
   mu0 Ms^2 V/6 (Section 6.2); M 1 = -1 up to the far-field approximation.
 """
+import os
+
 import numpy as np
 import pytest
 
-from oracle import dense, energy, geometry, h2
+from oracle import energy, geometry, h2
 from workloads import cases, rhs
 
 torch = pytest.importorskip("torch")
@@ -31,6 +34,9 @@ def run(op, u1):
     op.apply(d1, d2)
     torch.cuda.synchronize()
     return d2.cpu().numpy()
+
+
+GOLDEN_ROWS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere_l7_dense_rows.npz")
 
 
 def relerr(a, b):
@@ -61,18 +67,21 @@ def test_sphere_l7_sampled_columns(lib, sphere_l7, prec, tol):
     assert np.all(err <= tol), err
 
 
-def test_sphere_l7_dense_rows(lib, sphere_l7):
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sphere_l7_dense_rows(lib, sphere_l7, prec):
+    # 1000 exact rows of M u1 (tests/golden/make_dense_rows.py, oracle only)
     c, xyz, tri, _, _ = sphere_l7
+    g = np.load(GOLDEN_ROWS)
+    rows, ref = g["rows"], g["values"]
     n = xyz.shape[0]
+    assert int(g["n_nodes"]) == n
     u = np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(n, 8, 0)])
-    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp32")
-    out = run(op, u)
-    rows = np.random.default_rng(2).choice(n, 64, replace=False)
-    ref = dense.apply_rows(xyz, tri, u, rows)
-    err = relerr(out[:, rows], ref)
-    # interpolation error of the H2 approximation at order 4 (not arithmetic:
-    # FP32 and FP64 agree to 2e-7): measured 2.4e-4 for the smooth u1 = z and
-    # ~3e-5 for N(0,1) columns on these rows; the paper fixes no bound here
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec)
+    err = relerr(run(op, u)[:, rows], ref)
+    print(f"{prec}: H2 vs 1000 dense rows, per column: {np.array2string(err, precision=2)}")
+    # interpolation error of the H2 approximation at order 4, not arithmetic
+    # (FP32 and FP64 agree to 3e-7): ~2.4e-4 for the smooth u1 = z and ~3e-5
+    # for N(0,1) columns; the paper fixes no bound here
     assert err[0] <= 5e-4 and np.all(err[1:] <= 1e-4), err
 
 
@@ -104,3 +113,39 @@ def test_sphere_l8_uniform_magnetisation(lib, sphere_l8):
     e = energy.demag_energy_z(xyz, tri, out[0])
     assert abs(e / (vol / 6.0) - 1.0) < 1e-3
     assert np.max(np.abs(out[1] + 1.0)) < 2e-3
+
+
+@pytest.fixture(scope="module")
+def film():
+    c = cases.CASES["film"]
+    xyz, tri = cases.mesh_of(c.mesh)
+    return c, xyz, tri
+
+
+def test_film_sampled_columns_fp64(lib, film):
+    c, xyz, tri = film
+    H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False)
+    u = unit_columns(xyz.shape[0], 16, 13)
+    ref = H.apply(u)
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp64")
+    err = relerr(run(op, u), ref)
+    assert np.all(err <= 1e-12), err
+
+
+def test_film_fp32_smooth_fields(lib, film):
+    # FP32 against the FP64 path (itself the oracle's to 1e-12) on the four
+    # smooth fields.  On the flat faces the far field of coplanar clusters is
+    # a sum of large terms that cancel (the normal derivative of the kernel
+    # taken through Chebyshev points across a box only alpha = 0.1 of its
+    # length thick), so FP32 rounding is amplified: measured 4.5e-6, against
+    # 2e-7 on the sphere
+    c, xyz, tri = film
+    u = rhs.smooth_fields(xyz, c.nrhs)
+    outs = {}
+    for prec in ("fp64", "fp32"):
+        op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec)
+        outs[prec] = run(op, u)
+        op.close()
+    err = relerr(outs["fp32"], outs["fp64"])
+    print(f"film fp32 vs fp64: {np.array2string(err, precision=2)}")
+    assert np.all(err <= 1e-5), err

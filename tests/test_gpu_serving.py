@@ -43,19 +43,38 @@ def test_offload_reload_roundtrip(mods):
         assert np.array_equal(_apply(op, u), before)
 
 
+def test_async_reload_then_apply_on_another_stream(mods):
+    # the reload's copies are only enqueued on s1; an apply launched at once on
+    # s2 must wait for them on the device (the copies take milliseconds, the
+    # apply a fraction of one, so a missing wait would read partial buffers)
+    h2dlp, _ = mods
+    xyz, tri = meshes.icosphere(5, 0.01, 0)
+    op = h2dlp.Operator(xyz, tri, order=4, leaf=64, precision="fp32")
+    u = np.random.default_rng(1).normal(size=(16, xyz.shape[0]))
+    before = _apply(op, u)
+    d1 = torch.tensor(u, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for _ in range(2):
+        d2 = torch.full_like(d1, float("nan"))
+        torch.cuda.synchronize()
+        op.offload()
+        op.reload(stream=s1)
+        op.apply(d1, d2, stream=s2)
+        torch.cuda.synchronize()
+        assert np.array_equal(d2.cpu().numpy(), before)
+
+
 def test_mix_equals_alone_under_budget(mods):
     h2dlp, serving = mods
     ms = _meshes()
     specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32") for k, (x, t) in ms.items()]
     backend = serving.GpuBackend(0)
     sizes = {s.mesh_id: backend.plan_bytes(s) for s in specs}
-    n_slots = 3
-    slot_bytes = n_slots * max(w for _, w in sizes.values())
     res = sorted(r for r, _ in sizes.values())
-    budget = slot_bytes + res[-1] + res[-2] - 1          # never all three at once
-    srv = serving.Server(backend, budget, n_slots=n_slots, max_batch_rhs=24)
+    srv = serving.Server(backend, 0, n_slots=3, max_batch_rhs=24)
     for s in specs:
         srv.add_mesh(s)
+    srv.budget = srv.fixed_bytes() + res[-1] + res[-2] - 1     # never all three at once
     srv.prewarm()
     g = np.random.default_rng(4)
     t = np.cumsum(g.exponential(1 / 400.0, 60))

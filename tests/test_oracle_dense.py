@@ -120,3 +120,19 @@ def test_torus_azimuthal_gives_zero_potential():
     M = dense.dense_m(xyz, tri)
     u1 = np.full(xyz.shape[0], 0.7)
     np.testing.assert_allclose(M @ u1 + u1, 0.0, atol=1e-13)
+
+
+def test_stored_dense_rows_are_the_oracles():
+    # the 1000-row fixture of the 163842-node sphere: spot-check three rows
+    # against a fresh evaluation (tests/golden/make_dense_rows.py wrote it)
+    import os
+    from workloads import cases, rhs
+    g = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere_l7_dense_rows.npz"))
+    c = cases.CASES["sphere_l7"]
+    xyz, tri = cases.mesh_of(c.mesh)
+    rows = np.random.default_rng(2).choice(xyz.shape[0], 1000, replace=False)
+    assert np.array_equal(g["rows"], rows)
+    u = np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(xyz.shape[0], 8, 0)])
+    pick = [0, 499, 999]
+    fresh = dense.m_rows(xyz, tri, rows[pick]) @ u.T
+    np.testing.assert_allclose(fresh.T, g["values"][:, pick], rtol=1e-12, atol=1e-14)

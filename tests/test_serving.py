@@ -46,7 +46,7 @@ class FakeBackend(Backend):
         op.on_device = False
         self.device_bytes -= self.sizes[op.mesh_id][0]
 
-    def reload(self, op):
+    def reload(self, op, slot=None):
         self.log.append(("reload", op.mesh_id))
         op.on_device = True
         self._grow(self.sizes[op.mesh_id][0])
@@ -55,7 +55,7 @@ class FakeBackend(Backend):
         if op.on_device:
             self.device_bytes -= self.sizes[op.mesh_id][0]
 
-    def make_slots(self, n, workspace_bytes):
+    def make_slots(self, n, workspace_bytes, max_values=0):
         self._grow(n * workspace_bytes)
         return [{"id": q} for q in range(n)]
 
@@ -179,3 +179,34 @@ def test_launch_failure_fails_only_that_mesh():
 def test_invalid_server_arguments():
     with pytest.raises(ValueError):
         Server(FakeBackend(SIZES), 100, n_slots=0)
+
+
+def test_victim_is_smallest_operator_that_makes_room():
+    be = FakeBackend(SIZES)
+    srv = Server(be, budget_bytes=20 + 800, n_slots=2)
+    for s in _specs(MESHES):
+        srv.add_mesh(s)
+    a, b, c = (srv.meshes[k] for k in "abc")
+    assert srv._make_resident(a) and srv._make_resident(b)
+    a.last_used, b.last_used = 2.0, 1.0            # b is least recently used, but a alone makes room
+    assert srv._make_resident(c)
+    assert not a.on_device and b.on_device and c.on_device
+    # a (300) needs 200 more bytes: c (200) is the smallest idle operator that makes room
+    assert srv._make_resident(a)
+    assert not c.on_device and a.on_device and b.on_device
+    # c (200) with a budget of 400 next to a and b: no idle operator alone makes
+    # room for the 600 bytes over, so the largest (b) goes first, then a
+    srv.budget = 20 + 400
+    be.log.clear()
+    assert srv._make_resident(c)
+    assert [e[1] for e in be.log if e[0] == "offload"] == ["b", "a"] and c.on_device
+
+
+def test_request_wider_than_batch_limit_is_rejected():
+    be = FakeBackend(SIZES)
+    srv = Server(be, budget_bytes=10_000, n_slots=1, max_batch_rhs=3)
+    for s in _specs(MESHES):
+        srv.add_mesh(s)
+    reqs = [Request(0, "a", np.ones((4, 30)), 0.0), Request(1, "a", np.ones((3, 30)), 0.0)]
+    stats = srv.run(reqs)
+    assert reqs[0].error and reqs[1].error is None and stats["served"] == 1
