@@ -28,6 +28,8 @@ METRIC = "H² DLP matvec boundary GDOF/s + %HBM roofline; serve p50/p99 at 1e-6 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ("paper_1811_05731_amd/csrc/apply_kernels.hip", "paper_1811_05731_amd/csrc/layout.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "coupling_sphere_l8_traffic.json")
+RHS_PER_PASS = 16
+DEFAULT_COUPLING = "generated"
 
 
 def kernel_hash() -> str:
@@ -223,7 +225,7 @@ def cpu_baseline(xyz, tri, case, nrhs: int, frac: float = 0.01, seed: int = 7) -
     }
 
 
-def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4) -> dict:
+def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4, coupling: str = "stored") -> dict:
     """The serving mix: Poisson arrivals of 1..16-column requests over six resident meshes.
 
     Spheres (levels 4-7), the thin film and a torus, FP32 operators; the HBM
@@ -237,7 +239,8 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4)
     specs = []
     for spec, order, leaf in cases.SERVING_MESHES:
         xyz, tri = cases.mesh_of(spec)
-        specs.append(serving.MeshSpec(spec.name, xyz, tri, order=order, leaf=leaf, eta=2.0, precision="fp32"))
+        specs.append(serving.MeshSpec(spec.name, xyz, tri, order=order, leaf=leaf, eta=2.0, precision="fp32",
+                                      coupling=coupling))
     srv = serving.Server(backend, 0, n_slots=n_slots, max_batch_rhs=64)
     for s in specs:
         srv.add_mesh(s)
@@ -261,8 +264,41 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4)
             "throughput_GDOF_s": round(st["throughput_GDOF_s"], 4), "batches": st["batches"],
             "budget_GB": round(budget / 1e9, 2), "operators_GB": round(sum(resident) / 1e9, 2),
             "slots_GB": round(srv.fixed_bytes() / 1e9, 2),
-            "slots": n_slots, "precision": "fp32", "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
+            "slots": n_slots, "precision": "fp32", "coupling": coupling, "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
             "reloads": sum(st["reloads"].values()), "offloads": sum(st["offloads"].values())}
+
+
+MFMA_PEAK_TFS = {"fp32": 157.3, "fp64": 78.6}     # dense MFMA peaks of MI355X
+
+
+def coupling_flops(st) -> float:
+    """Algorithmic flops of one coupling launch on 16 right-hand sides: 2 k^2 per column and block."""
+    return 2.0 * st.coupling_entries * RHS_PER_PASS
+
+
+def near_field_alg_bytes(st, elem: int, n_nodes: int) -> int:
+    """Algorithmic bytes of one near-field launch (16 columns): the near blocks
+    and FP64 near-singular entries once, x (and x64 on the FP32 path) read, y64 written."""
+    vec = n_nodes * RHS_PER_PASS * (elem + 8 + (8 if elem == 4 else 0))
+    return st.bytes_near + vec
+
+
+def roofline_of(st, prec: str, coupling: str, kernels: dict, n_nodes: int) -> dict:
+    """Roofline record of the coupling kernel from its HIP-event time."""
+    cpl_ms, cpl_n = kernels["coupling"]
+    avg = cpl_ms / max(cpl_n, 1)
+    ev = 8 if prec == "fp64" else 4
+    if coupling == "generated":            # no coupling bytes: bound by the MFMA pipe
+        fl = coupling_flops(st)
+        ach = fl / (avg * 1e-3) / 1e12
+        peak = MFMA_PEAK_TFS[prec]
+        return {"bound": "mfma", "kernel": "coupling", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "alg_flops_per_launch": fl, "avg_launch_ms": round(avg, 4)}
+    es = {"fp64": 8, "bf16x6": 6}.get(prec, 4)
+    b = coupling_alg_bytes(st, es, ev)
+    ach = b / (avg * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": "coupling", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": b, "avg_launch_ms": round(avg, 4)}
 
 
 def main():
@@ -272,8 +308,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sphere_l8")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
+    ap.add_argument("--coupling", default=DEFAULT_COUPLING, choices=("stored", "generated"))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-variants", action="store_true", help="skip the FP64 comparison path")
+    ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and coupling modes")
     ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     args = ap.parse_args()
@@ -295,14 +332,18 @@ def main():
     d_u1 = torch.tensor(u1, device=dev)
     d_u2 = torch.empty_like(d_u1)
 
+    def build(prec, coupling):
+        return h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
+                              coupling=coupling)
+
     t0 = time.perf_counter()
-    op = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=args.precision, device=0)
+    op = build(args.precision, args.coupling)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     st = op.stats
     elem = 8 if args.precision == "fp64" else 4
-    print(f"# built {case.name} {args.precision}: N={n} clusters={st.n_clusters} far={st.n_far} near={st.n_near} "
-          f"resident={st.bytes_resident / 1e9:.2f} GB in {build_s:.1f} s", file=sys.stderr, flush=True)
+    print(f"# built {case.name} {args.precision} {args.coupling}: N={n} clusters={st.n_clusters} far={st.n_far} "
+          f"near={st.n_near} resident={st.bytes_resident / 1e9:.2f} GB in {build_s:.1f} s", file=sys.stderr, flush=True)
 
     # timed region: HIP events around the coupling launches only (the roofline
     # kernel); the per-kind breakdown comes from a separate profiled pass
@@ -311,27 +352,29 @@ def main():
     _, breakdown = time_path(op, d_u1, d_u2, 5, 0, profile=True)
     diag_main = op.export_diagonal()
     value = n * nrhs / (ms * 1e-3) / 1e9
-    cpl_ms, cpl_n = kernels["coupling"]
-    cpl_avg_ms = cpl_ms / max(cpl_n, 1)
-    b_cpl = coupling_alg_bytes(st, elem, elem)
-    achieved = b_cpl / (cpl_avg_ms * 1e-3) / 1e9
-    b_apply = apply_alg_bytes(st, elem, n, nrhs)
-    traffic = None
+    roof = roofline_of(st, args.precision, args.coupling, kernels, n)
+    roof["traffic"] = None
     if os.path.exists(TRAFFIC_FILE):
         rec = json.load(open(TRAFFIC_FILE))
         if rec.get("kernel_hash") == kernel_hash() and rec.get("precision") == args.precision \
-                and rec.get("workload") == args.workload:
-            traffic = rec.get("bytes_per_launch")
+                and rec.get("workload") == args.workload and rec.get("coupling", "stored") == args.coupling:
+            roof["traffic"] = rec.get("bytes_per_launch")
+    b_apply = apply_alg_bytes(st, elem, n, nrhs)
+    lo_ms, lo_n = breakdown["near_field"]
+    b_lo = near_field_alg_bytes(st, elem, n)
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
         "config": {"workload": describe(case, n, tri.shape[0], rhs_text),
                    "nodes": n, "rhs": nrhs, "order": case.order, "leaf": case.leaf, "eta": case.eta,
-                   "precision": args.precision},
-        "roofline": {"bound": "hbm", "kernel": "coupling", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "alg_bytes_per_launch": b_cpl, "avg_launch_ms": round(cpl_avg_ms, 4)},
+                   "precision": args.precision, "coupling": args.coupling},
+        "roofline": roof,
+        # the near-field kernel is the apply's HBM-bound part in either mode
+        "roofline_near_field": {"bound": "hbm", "achieved": round(b_lo / (lo_ms / max(lo_n, 1) * 1e-3) / 1e9, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(b_lo / (lo_ms / max(lo_n, 1) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "alg_bytes_per_launch": b_lo, "avg_launch_ms": round(lo_ms / max(lo_n, 1), 4)},
         "apply_hbm_frac": round(b_apply / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "copy_GBps": None,
         "apply_alg_bytes": b_apply,
@@ -348,40 +391,44 @@ def main():
     op.close()
     copy_gbs = copy_bandwidth(dev)
     out["copy_GBps"] = round(copy_gbs, 1)
-    out["roofline"]["frac_of_copy"] = round(achieved / copy_gbs, 4)
     out["apply_copy_frac"] = round(b_apply / (ms * 1e-3) / 1e9 / copy_gbs, 4)
 
-    if not args.no_variants and args.precision == "fp32":
+    if not args.no_variants:
         variants, outs = {}, {}
-        for prec in ("fp64", "bf16x3", "bf16x6"):
-            if prec.startswith("bf16") and case.order > 5:
+        configs = [("fp64", "stored"), ("fp64", "generated"), ("fp32", "stored"), ("fp32", "generated"),
+                   ("bf16x3", "stored"), ("bf16x6", "stored")]
+        for prec, cpl in configs:
+            if (prec, cpl) == (args.precision, args.coupling):
                 continue
-            opv = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0)
+            if (prec.startswith("bf16") or cpl == "generated") and case.order > 5:
+                continue
+            opv = build(prec, cpl)
             msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=("coupling",))
-            outs[prec] = d_u2.cpu().numpy()
-            ev = 8 if prec == "fp64" else 4                      # bytes per vector value
-            es = {"fp64": 8, "bf16x6": 6}.get(prec, 4)            # bytes per coupling entry
-            cv_ms, cv_n = kv["coupling"]
-            variants[prec] = {
-                "value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
-                "coupling_GBps": round(coupling_alg_bytes(opv.stats, es, ev) / (cv_ms / max(cv_n, 1) * 1e-3) / 1e9, 1),
-                "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            key = prec if cpl == "stored" else f"{prec}_generated"
+            outs[key] = d_u2.cpu().numpy()
+            ev = 8 if prec == "fp64" else 4
+            variants[key] = {"value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
+                             "coupling": roofline_of(opv.stats, prec, cpl, kv, n),
+                             "resident_GB": round(opv.stats.bytes_resident / 1e9, 2),
+                             "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9
+                                                     / HBM_PEAK_GBS, 4)}
             opv.close()
-        ref = outs["fp64"]
-        rel = lambda a: float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)):.3e}")  # noqa: E731
-        out["fp32_vs_fp64_gpu_rel_err"] = rel(u2_main)
-        # the same error relative to |K u1| (the far-reaching part, without the diagonal)
-        k_ref = ref - diag_main[None, :] * u1
-        out["fp32_vs_fp64_gpu_rel_err_of_K"] = float(
-            f"{np.max(np.linalg.norm(u2_main - ref, axis=1) / np.linalg.norm(k_ref, axis=1)):.3e}")
-        for prec in ("bf16x3", "bf16x6"):
-            if prec in outs:
-                variants[prec]["vs_fp64_gpu_rel_err"] = rel(outs[prec])
+        ref = outs.get("fp64") if args.precision != "fp64" or args.coupling != "stored" else u2_main
+        if ref is not None:
+            rel = lambda a: float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)):.3e}")  # noqa: E731
+            out["vs_fp64_gpu_rel_err"] = rel(u2_main)
+            # the same error relative to |K u1| (the far-reaching part, without the diagonal)
+            k_ref = ref - diag_main[None, :] * u1
+            out["vs_fp64_gpu_rel_err_of_K"] = float(
+                f"{np.max(np.linalg.norm(u2_main - ref, axis=1) / np.linalg.norm(k_ref, axis=1)):.3e}")
+            for key, val in outs.items():
+                if key != "fp64":
+                    variants[key]["vs_fp64_gpu_rel_err"] = rel(val)
         out["variants"] = variants
 
     if not args.no_serve:
         print("# serving the mixed request stream", file=sys.stderr, flush=True)
-        out["serving"] = serve_bench()
+        out["serving"] = serve_bench(coupling=args.coupling)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)        # 1 GiB

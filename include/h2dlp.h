@@ -65,7 +65,14 @@ typedef struct {
  * (admissibility max(diam_t, diam_s) <= eta dist(t, s)); alpha in [0, 1]
  * (each cluster box side is widened to at least alpha times its longest side);
  * device: HIP ordinal or -1 for the current device; stream: hipStream_t for the
- * build kernels, NULL for the null stream. */
+ * build kernels, NULL for the null stream.
+ * coupling: H2DLP_COUPLING_STORED keeps every coupling matrix S_ts in device
+ * memory (k^2 values per admissible block, read once per apply);
+ * H2DLP_COUPLING_GENERATED keeps only each cluster's box and recomputes
+ * S_ts(nu, mu) = 1/(4 pi |eta^t_nu - eta^s_mu|) (Section 4: the kernel at the
+ * interpolation points) inside the apply, from the FP64 difference of the box
+ * centres plus the two points' offsets; the same operator without the
+ * coupling bytes (FP64 and FP32 precision, order <= 5; else ENOTSUP). */
 typedef struct {
     int    order;
     int    leaf;
@@ -74,7 +81,11 @@ typedef struct {
     double alpha;
     int    device;
     void*  stream;
+    int    coupling;
 } h2dlp_options;
+
+#define H2DLP_COUPLING_STORED     0
+#define H2DLP_COUPLING_GENERATED  1
 
 typedef struct h2dlp_ctx* h2dlp_handle;
 
@@ -94,7 +105,8 @@ typedef struct {
     double  compression;        /* 1 - (H2 bytes)/(8 N^2), the paper's ratio r (Section 6.1) */
 } h2dlp_stats;
 
-/* Fill *opt with defaults: order 4, leaf 32, eta 2, FP64, alpha 0.1, device -1, stream NULL. */
+/* Fill *opt with defaults: order 4, leaf 32, eta 2, FP64, alpha 0.1, device -1,
+ * stream NULL, coupling STORED. */
 void h2dlp_default_options(h2dlp_options* opt);
 
 /* Build the H2 operator for `mesh` (copied; the caller may free it on return).
@@ -172,14 +184,15 @@ const char* h2dlp_last_error(void);
 
 /* Kernel timing with hipEvents recorded around the launches of the apply, on
  * the stream each launch goes to.  Kinds: 0 permute, 1 leaf forward, 2 upward
- * transfer, 3 coupling, 4 downward transfer, 5 leaf backward + near field +
- * diagonal (+ un-permute).  `enable` is a bit mask: bit q records kind q
+ * transfer, 3 coupling, 4 downward transfer, 5 leaf backward V_t yhat_t (+
+ * un-permute), 6 near field + diagonal.  The near field runs on a stream of
+ * the handle's own, concurrently with kinds 1-4, so kind times overlap.  `enable` is a bit mask: bit q records kind q
  * (0 = off, H2DLP_PROFILE_ALL = every kind); record only the kinds you need,
  * since every event pair adds a little time to the stream.
  * h2dlp_profile_read synchronises the recorded events and returns the summed
- * milliseconds and launch counts per kind (n_kinds <= 6). */
-#define H2DLP_NKINDS 6
-#define H2DLP_PROFILE_ALL 0x3f
+ * milliseconds and launch counts per kind (n_kinds <= 7). */
+#define H2DLP_NKINDS 7
+#define H2DLP_PROFILE_ALL 0x7f
 int h2dlp_profile(h2dlp_handle h, int enable);
 int h2dlp_profile_read(h2dlp_handle h, double* ms, int64_t* launches, int n_kinds, int reset);
 

@@ -117,6 +117,7 @@ struct h2dlp_ctx {
     void* d_e = nullptr;
     void* d_pool_wt = nullptr;
     void* d_pool_s = nullptr;
+    double* d_cgeo = nullptr;        // generated coupling: per cluster centre xyz, half extent xyz
     void* d_pool_leaf = nullptr;
     ItemDesc* d_items_fwd = nullptr;
     BlkDesc* d_blks_fwd = nullptr;
@@ -124,6 +125,8 @@ struct h2dlp_ctx {
     BlkDesc* d_blks_cpl = nullptr;
     ItemDesc* d_items_leaf = nullptr;
     BlkDesc* d_blks_leaf = nullptr;
+    ItemDesc* d_items_near = nullptr;   // the leaf items without their V_t block
+    ItemDesc* d_items_v = nullptr;      // the leaf items' V_t block alone
     int64_t* d_ns_off = nullptr;
     int32_t* d_ns_pos = nullptr;
     double* d_ns_val = nullptr;
@@ -137,6 +140,8 @@ struct h2dlp_ctx {
     bool offloaded = false;
     struct Parked { void** field; void* host; size_t bytes; bool scratch; };
     std::vector<bool> empty_field;   // fields() entries that hold no bytes (NULL after the build)
+    // the near field runs on this stream while the far-field chain runs on the caller's
+    hipStream_t side = nullptr;
     // a reload enqueued on a stream: every later use of the device buffers waits for it
     hipEvent_t ready = nullptr;
     bool ready_pending = false;
@@ -144,10 +149,11 @@ struct h2dlp_ctx {
     // host-side plan
     std::vector<int32_t> child0, child1, parent;
     std::vector<double> boxes;
+    std::vector<double> cgeo;
     std::vector<LeafDesc> leaves, vleaves;
     std::vector<FarDesc> fars;
     std::vector<NearDesc> nears;
-    std::vector<ItemDesc> items_fwd, items_cpl, items_leaf;
+    std::vector<ItemDesc> items_fwd, items_cpl, items_leaf, items_near, items_v;
     std::vector<BlkDesc> blks_fwd, blks_cpl, blks_leaf;
     int64_t off_wt = 0, off_s = 0, off_l = 0;
     h2dlp_stats st{};
@@ -165,6 +171,7 @@ struct h2dlp_ctx {
         (void)hipSetDevice(device);
         for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         if (ready) { (void)hipEventSynchronize(ready); (void)hipEventDestroy(ready); }
+        if (side) { (void)hipStreamSynchronize(side); (void)hipStreamDestroy(side); }
         for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
         for (auto& p : parked) if (p.host) (void)hipHostFree(p.host);
         (void)hipSetDevice(cur);
@@ -175,9 +182,11 @@ struct h2dlp_ctx {
         return {{(void**)&d_perm, false}, {(void**)&d_iperm, false}, {(void**)&d_diag, false},
                 {(void**)&d_child0, false}, {(void**)&d_child1, false}, {(void**)&d_parent, false},
                 {(void**)&d_e, false}, {(void**)&d_pool_wt, false}, {(void**)&d_pool_s, false},
+                {(void**)&d_cgeo, false},
                 {(void**)&d_pool_leaf, false}, {(void**)&d_items_fwd, false}, {(void**)&d_blks_fwd, false},
                 {(void**)&d_items_cpl, false}, {(void**)&d_blks_cpl, false}, {(void**)&d_items_leaf, false},
-                {(void**)&d_blks_leaf, false}, {(void**)&d_ns_off, false}, {(void**)&d_ns_pos, false},
+                {(void**)&d_blks_leaf, false}, {(void**)&d_items_near, false}, {(void**)&d_items_v, false},
+                {(void**)&d_ns_off, false}, {(void**)&d_ns_pos, false},
                 {(void**)&d_ns_val, false}, {(void**)&d_ws, true}};
     }
     size_t bytes_of(void* p) const {
@@ -283,6 +292,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     for (size_t b = 0; b < S.far.size(); ++b)
         far_by_t[h->gid_of_pre[S.far[b].first]].push_back(h->gid_of_pre[S.far[b].second]);
     int64_t off_s = 0;
+    const bool gen = o->coupling == H2DLP_COUPLING_GENERATED;
     const int kp = bf16_parts(h->prec) > 0 ? bf16s_cols(k) : coupling_cols(k);
     h->kp = kp;
     for (int32_t g = 0; g < C; ++g) {
@@ -290,6 +300,10 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         std::sort(lst.begin(), lst.end());
         h->items_cpl.push_back(ItemDesc{g * k, k, int32_t(h->blks_cpl.size()), int32_t(h->blks_cpl.size() + lst.size())});
         for (int32_t s : lst) {
+            if (gen) {                   // nothing stored: a_off names the source cluster
+                h->blks_cpl.push_back(BlkDesc{int64_t(s), k, s * k});
+                continue;
+            }
             off_s = align_block(off_s);
             h->fars.push_back(FarDesc{g, s, off_s});
             h->blks_cpl.push_back(BlkDesc{off_s, kp, s * k});
@@ -324,6 +338,10 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     h->n_items_fwd = int32_t(h->items_fwd.size());
     h->n_items_cpl = int32_t(h->items_cpl.size());
     h->n_items_leaf = int32_t(h->items_leaf.size());
+    for (const ItemDesc& d : h->items_leaf) {     // block 0 of a leaf item is V_t, the rest near blocks
+        h->items_near.push_back(ItemDesc{d.out_row, d.m, d.blk_begin + 1, d.blk_end});
+        h->items_v.push_back(ItemDesc{d.out_row, d.m, d.blk_begin, d.blk_begin + 1});
+    }
     h->rt_leaf = (o->leaf + 15) / 16;
     h->off_wt = off_wt;
     h->off_s = off_s;
@@ -354,12 +372,21 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     st.coupling_entries = int64_t(S.far.size()) * k * k;
     st.near_entries = near_entries;
     st.nearsing_entries = fp64 ? 0 : int64_t(S.ring_pos.size());
-    st.bytes_coupling = int64_t(h->elem_s * size_t(st.coupling_entries));
+    st.bytes_coupling = gen ? 0 : int64_t(h->elem_s * size_t(st.coupling_entries));
+    if (gen) {
+        h->cgeo.resize(size_t(6) * C);
+        for (int32_t g = 0; g < C; ++g)
+            for (int a = 0; a < 3; ++a) {
+                const double lo = h->boxes[6 * size_t(g) + a], hi = h->boxes[6 * size_t(g) + 3 + a];
+                h->cgeo[6 * size_t(g) + a] = 0.5 * (lo + hi);
+                h->cgeo[6 * size_t(g) + 3 + a] = 0.5 * (hi - lo);
+            }
+    }
     st.bytes_near = int64_t(e * size_t(near_entries));
     if (!fp64) st.bytes_near += int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8));
     st.bytes_bases = int64_t(e * size_t(2 * N * int64_t(k)));
     st.bytes_transfer = int64_t(e * size_t(C) * 3 * m * m);
-    st.bytes_other = int64_t(N * 8 + 3 * int64_t(C) * 4 + N * 8 +
+    st.bytes_other = int64_t(N * 8 + 3 * int64_t(C) * 4 + N * 8 + int64_t(h->cgeo.size()) * 8 +
                              (h->items_fwd.size() + h->items_cpl.size() + h->items_leaf.size()) * sizeof(ItemDesc) +
                              (h->blks_fwd.size() + h->blks_cpl.size() + h->blks_leaf.size()) * sizeof(BlkDesc));
     st.workspace_bytes = int64_t(h->ws_bytes);
@@ -395,9 +422,13 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_items_fwd = h->upload(h->items_fwd, &kept, stream);
     h->d_blks_fwd = h->upload(h->blks_fwd, &kept, stream);
     h->d_items_cpl = h->upload(h->items_cpl, &kept, stream);
+    if (!h->cgeo.empty()) h->d_cgeo = h->upload(h->cgeo, &kept, stream);
     h->d_blks_cpl = h->upload(h->blks_cpl, &kept, stream);
     h->d_items_leaf = h->upload(h->items_leaf, &kept, stream);
     h->d_blks_leaf = h->upload(h->blks_leaf, &kept, stream);
+    h->d_items_near = h->upload(h->items_near, &kept, stream);
+    h->d_items_v = h->upload(h->items_v, &kept, stream);
+    check(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "side stream");
     if (!fp64) {
         h->d_ns_off = h->upload(S.ring_off, &kept, stream);
         h->d_ns_pos = h->upload(S.ring_pos, &kept, stream);
@@ -429,8 +460,9 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf, stream),
           "row basis");
     check(launch_build_transfer(d_boxes, h->d_parent, C, m, h->prec, h->d_e, stream), "transfer");
-    check(launch_build_coupling(d_boxes, m, h->kp, d_far, int64_t(h->fars.size()), h->prec, h->d_pool_s, stream),
-          "coupling");
+    if (h->d_cgeo == nullptr)
+        check(launch_build_coupling(d_boxes, m, h->kp, d_far, int64_t(h->fars.size()), h->prec, h->d_pool_s, stream),
+              "coupling");
     check(launch_build_near(dm, d_near, int64_t(h->nears.size()), h->prec, h->d_pool_leaf,
                             fp64 ? nullptr : h->d_ns_off, fp64 ? nullptr : h->d_ns_pos, fp64 ? nullptr : h->d_ns_val,
                             stream),
@@ -514,9 +546,29 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
             rec_end(h, s, 2, ev);
         }
 
-        ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
+        // near field, diagonal and near-singular part into y64 on the side stream,
+        // overlapping the coupling products (HBM-bound there, MFMA- or HBM-bound
+        // here); forked after the latency-bound upward pass so as not to slow it
+        hipEvent_t fork = nullptr, join = nullptr;
+        check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "event");
+        check(hipEventCreateWithFlags(&join, hipEventDisableTiming), "event");
+        check(hipEventRecord(fork, s), "event record");
+        check(hipStreamWaitEvent(h->side, fork, 0), "fork");
+        ProductArgs nearp{h->d_items_near, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
+        LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
+        rec_begin(h, h->side, 6, &ev);
+        check(launch_product_leaf(nearp, epi, prec, h->side), "near field");
+        rec_end(h, h->side, 6, ev);
+        check(hipEventRecord(join, h->side), "event record");
+
         rec_begin(h, s, 3, &ev);
-        check(launch_coupling(cpl, k, prec, s), "coupling");
+        if (h->d_cgeo) {
+            ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_cgeo, xh, nullptr, yh};
+            check(launch_coupling_generated(cpl, m, prec, s), "coupling");
+        } else {
+            ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
+            check(launch_coupling(cpl, k, prec, s), "coupling");
+        }
         rec_end(h, s, 3, ev);
 
         for (int l = 1; l <= h->S.depth; ++l) {
@@ -525,10 +577,13 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
             rec_end(h, s, 4, ev);
         }
 
-        ProductArgs leaf{h->d_items_leaf, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
-        LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
+        // join, then y64 += V_t yhat_t and back to the caller's node order
+        check(hipStreamWaitEvent(s, join, 0), "join");
+        (void)hipEventDestroy(fork);
+        (void)hipEventDestroy(join);
+        ProductArgs leafv{h->d_items_v, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
         rec_begin(h, s, 5, &ev);
-        check(launch_product_leaf(leaf, epi, prec, s), "leaf output");
+        check(launch_product_add64(leafv, y64, prec, s), "leaf output");
         check(launch_unpermute(y64, io, N, nr, h->d_iperm, u2p, s), "unpermute");
         rec_end(h, s, 5, ev);
     }
@@ -548,6 +603,7 @@ void h2dlp_default_options(h2dlp_options* o) {
     o->alpha = 0.1;
     o->device = -1;
     o->stream = nullptr;
+    o->coupling = H2DLP_COUPLING_STORED;
 }
 
 static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle* out) {
@@ -566,6 +622,11 @@ static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_hand
         return fail(H2DLP_EINVAL, "unknown precision");
     if ((o->precision == H2DLP_BF16X3 || o->precision == H2DLP_BF16X6) && o->order > 5)
         return fail(H2DLP_ENOTSUP, "BF16X3 and BF16X6 need order <= 5 (k <= 128)");
+    if (o->coupling != H2DLP_COUPLING_STORED && o->coupling != H2DLP_COUPLING_GENERATED)
+        return fail(H2DLP_EINVAL, "unknown coupling mode");
+    if (o->coupling == H2DLP_COUPLING_GENERATED &&
+        (o->order > 5 || (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32)))
+        return fail(H2DLP_ENOTSUP, "generated coupling needs FP64 or FP32 and order <= 5");
     return H2DLP_OK;
 }
 

@@ -19,6 +19,8 @@
 // registers, four k-steps per lane load (layout.h); X rows come through L2.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
 #include "kernels.h"
 
 namespace h2dlp {
@@ -62,7 +64,7 @@ __device__ inline int xcd_item(int n_items) {
     return item < n_items ? item : -1;
 }
 
-enum { EPI_STORE = 0, EPI_LEAF = 1 };
+enum { EPI_STORE = 0, EPI_LEAF = 1, EPI_ADD64 = 2 };
 
 template <typename V>
 __device__ inline V ld(const unsigned char* base, unsigned byte_off) {
@@ -213,11 +215,21 @@ __global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogu
 #pragma unroll
                     for (int v = 0; v < 4; ++v) acc[r][v] += slot[(r * 4 + v) * 64 + lane];
             }
-        if (EPI == EPI_STORE && bg > 0) return;
+        if (EPI != EPI_LEAF && bg > 0) return;
     }
 
     const int M = it.m;
     const int q = lane & 15;
+    if (EPI == EPI_ADD64) {          // y64 += the item's rows (cluster order)
+#pragma unroll
+        for (int r = 0; r < RTW; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
+                if (row < M) epi.y64[(int64_t(it.out_row) + row) * RHS_TILE + q] += double(acc[r][v]);
+            }
+        return;
+    }
     if (EPI == EPI_STORE) {
 #pragma unroll
         for (int r = 0; r < RTW; ++r)
@@ -358,6 +370,247 @@ __global__ void __launch_bounds__(kThreads) k_coupling(ProductArgs a, int kvalid
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * r + Mfma<T>::row(lane >> 4, v);
             if (row < M) static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + q] = acc[r][v];
+        }
+}
+
+// Generated coupling products (orders 1..5): yhat_t = sum_s S_ts xhat_s with
+// S_ts(nu, mu) = 1/(4 pi |eta^t_nu - eta^s_mu|) computed in registers instead
+// of read from memory.  eta^t_nu - eta^s_mu = (c_t - c_s) + h_t o_nu - h_s o_mu,
+// with c the box centre, h the half extent and o the unit Chebyshev nodes: the
+// centre difference is taken in FP64 and rounded once, the offsets are at most
+// a box size, so the difference keeps the precision of T even for close
+// blocks.  1/(4 pi) is applied once to the output.
+//
+// The sum over mu may run in any order (B rows follow the same order), so the
+// 4 lane groups of the MFMA's K dimension are given columns that keep the
+// work separable: in the main part lane group g always has mu_x = 4 q + g
+// (q < m / 4) while (mu_y, mu_z) is the same for the whole wave in a k-step,
+// so |d|^2 = dx^2[row] + dy^2[row][mu_y] + dz^2[row][mu_z] from per-block
+// tables; the remaining mu_x (m mod 4 values, all m^2 pairs) form a tail of
+// k-steps with per-lane columns.  FP32 uses v_rsq_f32 and FP64 refines v_rsq_f64
+// with two Newton steps.
+struct UnitNodes {
+    double o[8];
+};
+
+template <typename T>
+__device__ inline T rsqrt_kernel(T d2);
+template <>
+__device__ inline float rsqrt_kernel<float>(float d2) {
+    return __builtin_amdgcn_rsqf(d2);
+}
+template <>
+__device__ inline double rsqrt_kernel<double>(double d2) {
+    double y = __builtin_amdgcn_rsq(d2);
+    const double hd = 0.5 * d2;
+    y = y * (1.5 - hd * y * y);
+    y = y * (1.5 - hd * y * y);
+    return y;
+}
+
+#ifndef H2DLP_GEN_PREFETCH
+#define H2DLP_GEN_PREFETCH 1   // FP32: load the next block's xhat rows during this block
+#endif
+#ifndef H2DLP_GEN_WAVES
+#define H2DLP_GEN_WAVES 2      // minimum waves per SIMD the register allocation must allow
+#endif
+
+// ROWS = false: the 4 waves split the item's blocks and meet in LDS; ROWS =
+// true (RT a multiple of 4): wave w owns row tiles [w RT/4, (w + 1) RT/4) of
+// every block, so each wave keeps a quarter of the accumulators and stores its
+// rows itself.
+template <typename T, int M, bool ROWS>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H2DLP_GEN_WAVES)))
+k_coupling_gen(ProductArgs a, UnitNodes un) {
+    typedef typename Mfma<T>::acc acc_t;
+    constexpr int K = M * M * M, MM = M * M, RTA = (K + 15) / 16;
+    static_assert(!ROWS || RTA % kWaves == 0, "row split needs a multiple of 4 row tiles");
+    constexpr int RT = ROWS ? RTA / kWaves : RTA;    // row tiles of this wave
+    constexpr int Q = M / 4, R = M % 4;
+    constexpr int KS_TAIL = (R * MM + 3) / 4;
+    extern __shared__ unsigned char smem_raw[];
+    T* red = reinterpret_cast<T*>(smem_raw);
+    // the nodes, and the target rows' offsets h_t o_nu from the box centre
+    // (the same for the 4 waves: all work on one target cluster)
+    __shared__ T su[8];
+    __shared__ T sot[3][16 * RTA];
+
+    const int item = xcd_item(a.n_items);
+    if (item < 0) return;
+    const ItemDesc it = a.items[item];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned lane = threadIdx.x & 63;
+    const int i = int(lane & 15), g = int(lane >> 4);
+    const double* geo = static_cast<const double*>(a.pool);
+    const T* xh = static_cast<const T*>(a.x0);
+    T u[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) u[l] = T(un.o[l]);
+#pragma unroll
+    for (int l = 0; l < M; ++l)
+        if (threadIdx.x == unsigned(l)) su[l] = u[l];
+    const int t = it.out_row / K;
+    const double ctx = geo[6 * t], cty = geo[6 * t + 1], ctz = geo[6 * t + 2];
+    if (threadIdx.x < 16 * RTA) {
+        const int nu = int(threadIdx.x) < K ? int(threadIdx.x) : 0;
+        T vx = u[0], vy = u[0], vz = u[0];
+#pragma unroll
+        for (int l = 1; l < M; ++l) {
+            vx = nu % M == l ? u[l] : vx;
+            vy = (nu / M) % M == l ? u[l] : vy;
+            vz = nu / MM == l ? u[l] : vz;
+        }
+        sot[0][threadIdx.x] = T(geo[6 * t + 3]) * vx;
+        sot[1][threadIdx.x] = T(geo[6 * t + 4]) * vy;
+        sot[2][threadIdx.x] = T(geo[6 * t + 5]) * vz;
+    }
+    __syncthreads();
+
+    acc_t acc[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) acc[r] = acc_t{0, 0, 0, 0};
+
+    const int r0 = ROWS ? w * RT : 0;                // first row tile of this wave
+    const int first = ROWS ? it.blk_begin : it.blk_begin + w;
+    const int stride = ROWS ? 1 : kWaves;
+    constexpr int NB = Q * MM + KS_TAIL;               // k-steps (B values) per block
+    constexpr bool kTables = ROWS;                     // few row tiles per wave: per-block distance tables
+
+    // B operands of a block: x rows through L2
+    auto load_b = [&](int b, T* bv) {
+        const T* X = xh + int64_t(a.blks[b].src) * RHS_TILE + i;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int p = 0; p < MM; ++p) bv[q * MM + p] = X[(4 * q + g + M * p) * RHS_TILE];
+#pragma unroll
+        for (int ts = 0; ts < KS_TAIL; ++ts) {
+            const int c = 4 * ts + g;
+            const int cc = c < R * MM ? c : 0;
+            const T v = X[(4 * Q + cc % R + M * (cc / R)) * RHS_TILE];
+            bv[Q * MM + ts] = c < R * MM ? v : T(0);
+        }
+    };
+    auto block = [&](int b, const T* bv) {
+        const int sc = int(a.blks[b].a_off);
+        const T dx0 = T(ctx - geo[6 * sc]), dy0 = T(cty - geo[6 * sc + 1]), dz0 = T(ctz - geo[6 * sc + 2]);
+        const T hsx = T(geo[6 * sc + 3]), hsy = T(geo[6 * sc + 4]), hsz = T(geo[6 * sc + 5]);
+        T ax[RT], ay[RT], az[RT];
+#pragma unroll
+        for (int r = 0; r < RT; ++r) {
+            ax[r] = dx0 + sot[0][16 * (r0 + r) + i];
+            ay[r] = dy0 + sot[1][16 * (r0 + r) + i];
+            az[r] = dz0 + sot[2][16 * (r0 + r) + i];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const T osx = hsx * su[4 * q + g];
+            T dx2[RT];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const T e = ax[r] - osx;
+                dx2[r] = e * e;
+            }
+            // |d|^2 = (dx^2 + dy^2)[row][mu_y] + dz^2[row][mu_z]
+            T dxy2[kTables ? RT : 1][kTables ? M : 1], dz2[kTables ? RT : 1][kTables ? M : 1];
+            if constexpr (kTables) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+#pragma unroll
+                    for (int l = 0; l < M; ++l) {
+                        const T ey = ay[r] - hsy * u[l], ez = az[r] - hsz * u[l];
+                        dxy2[r][l] = dx2[r] + ey * ey;
+                        dz2[r][l] = ez * ez;
+                    }
+            }
+#pragma unroll
+            for (int p = 0; p < MM; ++p) {
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    T d2;
+                    if constexpr (kTables) {
+                        d2 = dxy2[r][p % M] + dz2[r][p / M];
+                    } else {
+                        const T ey = ay[r] - hsy * u[p % M], ez = az[r] - hsz * u[p / M];
+                        d2 = dx2[r] + ey * ey + ez * ez;
+                    }
+                    const T sv = 16 * (r0 + r) + i < K ? rsqrt_kernel<T>(d2) : T(0);
+                    acc[r] = Mfma<T>::mma(sv, bv[q * MM + p], acc[r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int ts = 0; ts < KS_TAIL; ++ts) {
+            const int c = 4 * ts + g;
+            const bool ok = c < R * MM;
+            const int cc = ok ? c : 0;
+            const int p = cc / R;
+            const T osx = hsx * su[4 * Q + cc % R], osy = hsy * su[p % M], osz = hsz * su[p / M];
+#pragma unroll
+            for (int r = 0; r < RT; ++r) {
+                const T ex = ax[r] - osx, ey = ay[r] - osy, ez = az[r] - osz;
+                const T d2 = ex * ex + ey * ey + ez * ez;
+                const T sv = ok && 16 * (r0 + r) + i < K ? rsqrt_kernel<T>(d2) : T(0);
+                acc[r] = Mfma<T>::mma(sv, bv[Q * MM + ts], acc[r]);
+            }
+        }
+    };
+
+    if constexpr (sizeof(T) == 4 && H2DLP_GEN_PREFETCH) {
+        // FP32: the next block's B values are in flight while this block runs
+        T b0[NB], b1[NB];
+        int b = first;
+        if (b < it.blk_end) load_b(b, b0);
+        for (; b < it.blk_end; b += 2 * stride) {
+            const bool more = b + stride < it.blk_end;
+            if (more) load_b(b + stride, b1);
+            block(b, b0);
+            if (!more) break;
+            if (b + 2 * stride < it.blk_end) load_b(b + 2 * stride, b0);
+            block(b + stride, b1);
+        }
+    } else {
+        T b0[NB];
+        for (int b = first; b < it.blk_end; b += stride) {
+            load_b(b, b0);
+            block(b, b0);
+        }
+    }
+
+    const T scale = T(0.25 / 3.14159265358979323846);
+    if constexpr (ROWS) {                          // each wave stores its own rows
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * (r0 + r) + Mfma<T>::row(g, v);
+                if (row < K) static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + i] = acc[r][v] * scale;
+            }
+        return;
+    }
+    // fixed-order reduction of the 4 waves, then store rows < K scaled by 1/(4 pi)
+    if (w > 0) {
+        T* slot = red + (w - 1) * RT * 256;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) slot[(r * 4 + v) * 64 + lane] = acc[r][v];
+    }
+    __syncthreads();
+    if (w > 0) return;
+    for (int q = 1; q < kWaves; ++q) {
+        const T* slot = red + (q - 1) * RT * 256;
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[r][v] += slot[(r * 4 + v) * 64 + lane];
+    }
+#pragma unroll
+    for (int r = 0; r < RT; ++r)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * r + Mfma<T>::row(g, v);
+            if (row < K) static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + i] = acc[r][v] * scale;
         }
 }
 
@@ -632,7 +885,7 @@ hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nr
         return hipGetLastError();                                                                    \
     }
     H2DLP_CASE(1, 1) H2DLP_CASE(2, 1) H2DLP_CASE(4, 1) H2DLP_CASE(8, 1)
-    if (EPI == EPI_STORE) {
+    if (EPI != EPI_LEAF) {
         H2DLP_CASE(1, 2) H2DLP_CASE(2, 2) H2DLP_CASE(4, 2) H2DLP_CASE(8, 2)
         H2DLP_CASE(1, 4) H2DLP_CASE(2, 4) H2DLP_CASE(4, 4) H2DLP_CASE(8, 4)
     }
@@ -715,6 +968,31 @@ hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows
     return dispatch<float, EPI_STORE>(a, none, rtw, nrg, st);
 }
 
+hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipStream_t st) {
+    if (m < 1 || m > 5 || (prec != P_FP32 && prec != P_FP64)) return hipErrorInvalidValue;
+    const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
+    if (grid == 0) return hipSuccess;
+    UnitNodes un{};
+    for (int l = 0; l < m; ++l) un.o[l] = std::cos((2.0 * l + 1.0) * 3.14159265358979323846 / (2.0 * m));
+    const int rt = (m * m * m + 15) / 16;
+    const size_t lds = size_t(kWaves - 1) * rt * 256 * (prec == P_FP64 ? 8 : 4);
+#define H2DLP_GEN_LAUNCH(MM, ROWS)                                                                              \
+    if (prec == P_FP64)                                                                                         \
+        hipLaunchKernelGGL((k_coupling_gen<double, MM, ROWS>), dim3(grid), dim3(kThreads), lds, st, a, un);    \
+    else                                                                                                        \
+        hipLaunchKernelGGL((k_coupling_gen<float, MM, ROWS>), dim3(grid), dim3(kThreads), lds, st, a, un);
+    switch (m) {
+        case 1: H2DLP_GEN_LAUNCH(1, false) break;
+        case 2: H2DLP_GEN_LAUNCH(2, false) break;
+        case 3: H2DLP_GEN_LAUNCH(3, false) break;
+        case 4: H2DLP_GEN_LAUNCH(4, true) break;
+        case 5: H2DLP_GEN_LAUNCH(5, true) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef H2DLP_GEN_LAUNCH
+    return hipGetLastError();
+}
+
 hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st) {
     const int rt = (k + 15) / 16;
     if (prec == P_BF16X3 || prec == P_BF16X6) {
@@ -757,6 +1035,17 @@ hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st
     }
 #undef H2DLP_CPL
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hipStream_t st) {
+    const int rt = a.rt;
+    const int nrg = rt >= 4 ? 4 : pow2ceil(rt);       // one block per item: the waves split its rows
+    const int rtw = pow2ceil((rt + nrg - 1) / nrg);
+    if (rtw > 8) return hipErrorInvalidValue;
+    LeafEpilogue e{};
+    e.y64 = y64;
+    if (prec == P_FP64) return dispatch<double, EPI_ADD64>(a, e, rtw, nrg, st);
+    return dispatch<float, EPI_ADD64>(a, e, rtw, nrg, st);
 }
 
 hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st) {

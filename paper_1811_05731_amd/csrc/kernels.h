@@ -88,6 +88,11 @@ hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int 
 // Coupling products; for k <= 128 with ceil(k/16) a power of two the blocks are
 // stored k x coupling_cols(k) (zero columns beyond k) and a pipelined kernel runs.
 hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st);
+// y64 += sum_b A_b X_b of each item (FP64 accumulation target in cluster order)
+hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hipStream_t st);
+// Generated coupling (orders 1..5, FP32 or FP64): a.pool holds the per-cluster
+// centre and half extent (6 doubles, level-order ids), blks[b].a_off the source cluster.
+hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipStream_t st);
 inline int coupling_cols(int k) {
     const int rt = (k + 15) / 16;
     return (rt <= 8 && (rt & (rt - 1)) == 0) ? 16 * rt : k;

@@ -19,9 +19,10 @@ LIB_PATH = os.path.join(HERE, "libh2dlp.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 IO_F64, IO_F32 = 0, 1
-NKINDS = 6
-KIND_NAMES = ("permute", "leaf_forward", "upward", "coupling", "downward", "leaf_output")
+NKINDS = 7
+KIND_NAMES = ("permute", "leaf_forward", "upward", "coupling", "downward", "leaf_output", "near_field")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
+COUPLING = {"stored": 0, "generated": 1}        # H2DLP_COUPLING_STORED / _GENERATED
 
 
 class H2dlpError(RuntimeError):
@@ -38,7 +39,7 @@ class _Mesh(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("leaf", ctypes.c_int), ("eta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("device", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("coupling", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -158,7 +159,8 @@ class Operator:
     """A built H2 boundary operator resident on one GPU (owns its device memory)."""
 
     def __init__(self, xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0,
-                 precision="fp64", alpha: float = 0.1, device: int = -1, stream=None, plan_only: bool = False):
+                 precision="fp64", alpha: float = 0.1, device: int = -1, stream=None, plan_only: bool = False,
+                 coupling: str = "stored"):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         tri = np.ascontiguousarray(tri, dtype=np.int32)
         if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3:
@@ -170,6 +172,7 @@ class Operator:
         opt.order, opt.leaf, opt.eta, opt.alpha, opt.device = order, leaf, eta, alpha, device
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         opt.stream = stream
+        opt.coupling = COUPLING[coupling]
         h = ctypes.c_void_p()
         entry = _lib.h2dlp_plan if plan_only else _lib.h2dlp_build_ex
         _check(entry(ctypes.byref(mesh), ctypes.byref(opt), ctypes.byref(h)))
@@ -268,9 +271,10 @@ class Operator:
         return {KIND_NAMES[q]: (ms[q], n[q]) for q in range(NKINDS)}
 
 
-def plan(xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64", alpha: float = 0.1):
+def plan(xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64", alpha: float = 0.1,
+         coupling: str = "stored"):
     """Host-only structure and byte counts (no GPU needed)."""
-    return Operator(xyz, tri, order, leaf, eta, precision, alpha, plan_only=True)
+    return Operator(xyz, tri, order, leaf, eta, precision, alpha, plan_only=True, coupling=coupling)
 
 
 def last_error() -> str:

@@ -38,6 +38,7 @@ class MeshSpec:
     leaf: int = 64
     eta: float = 2.0
     precision: str = "fp32"
+    coupling: str = "stored"          # "stored" | "generated" (coupling matrices recomputed in the apply)
 
     @property
     def n_nodes(self) -> int:
@@ -111,12 +112,13 @@ class GpuBackend(Backend):
         self.dev_index = device
 
     def plan_bytes(self, spec):
-        p = self.h2dlp.plan(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision)
+        p = self.h2dlp.plan(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
+                            coupling=spec.coupling)
         return p.stats.bytes_resident, p.stats.workspace_bytes
 
     def build(self, spec):
         return self.h2dlp.Operator(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
-                                   device=self.dev_index)
+                                   device=self.dev_index, coupling=spec.coupling)
 
     def offload(self, op):
         op.offload()

@@ -48,6 +48,9 @@ def test_argument_errors():
     assert _plan_rc(xyz, tri, order=6, precision="bf16x3") == h2dlp.ENOTSUP
     assert _plan_rc(xyz, tri, order=6, precision="bf16x6") == h2dlp.ENOTSUP
     assert _plan_rc(xyz, tri, order=5, precision="bf16x6") == 0
+    assert _plan_rc(xyz, tri, order=6, coupling="generated") == h2dlp.ENOTSUP
+    assert _plan_rc(xyz, tri, order=4, precision="bf16x3", coupling="generated") == h2dlp.ENOTSUP
+    assert _plan_rc(xyz, tri, order=5, precision="fp32", coupling="generated") == 0
     lib = h2dlp.library()
     out = ctypes.c_void_p()
     opt = h2dlp._Options()
@@ -118,6 +121,9 @@ def test_plan_sizes():
     assert s3.bytes_coupling == 4 * s.coupling_entries and s6.bytes_coupling == 6 * s.coupling_entries
     assert s6.bytes_resident - s3.bytes_resident == 2 * s.coupling_entries   # k = 64: no padding columns
     assert s6.bytes_near == s32.bytes_near and s6.bytes_bases == s32.bytes_bases
+    sg = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, precision="fp32", coupling="generated").stats
+    assert sg.bytes_coupling == 0 and sg.coupling_entries == s.coupling_entries
+    assert s32.bytes_resident - sg.bytes_resident == 4 * s.coupling_entries - 48 * s.n_clusters
     r, w = h2dlp.plan(xyz, tri).bytes()
     assert w > 0 and r > w
 

@@ -175,3 +175,45 @@ def test_workspace_and_streams(lib, sphere_l4):
     with pytest.raises(lib.H2dlpError) as e:
         op.apply(d_u1, outs[0], workspace=small)
     assert e.value.code == lib.ENOMEM
+
+
+# generated coupling: S_ts computed inside the apply from the box geometry
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("order", [1, 2, 3, 4, 5])
+def test_generated_coupling_every_order(lib, order, prec):
+    xyz, tri = meshes.icosphere(3, 0.01, 4)
+    H = h2.H2Oracle(xyz, tri, order=order, leaf=16, eta=2.0)
+    u = rhs.normal_rhs(xyz.shape[0], 3, order)
+    ref = H.apply(u)
+    op = lib.Operator(xyz, tri, order=order, leaf=16, eta=2.0, precision=prec, coupling="generated")
+    assert op.stats.n_far > 0 and op.stats.bytes_coupling == 0
+    err = relerr(run(op, u), ref)
+    print(f"generated {prec} order {order}: max rel err {err.max():.3e}")
+    assert np.all(err <= TOL[prec]), err
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_generated_coupling_columns(lib, sphere_l4, prec):
+    xyz, tri, H, _, _ = sphere_l4
+    op = lib.Operator(xyz, tri, order=4, leaf=32, eta=2.0, precision=prec, coupling="generated")
+    u = rhs.normal_rhs(xyz.shape[0], 37, 5)
+    ref = H.apply(u)
+    full = run(op, u)
+    assert np.all(relerr(full, ref) <= TOL[prec])
+    for q in (0, 15, 16, 36):
+        assert np.array_equal(run(op, u[q])[0], full[q])
+    assert np.array_equal(run(op, u), full)
+
+
+@pytest.mark.parametrize("mesh,order", [
+    (lambda: meshes.cuboid(200.0, 150.0, 20.0, 5.0, 0.5, 0), 4),
+    (lambda: meshes.torus(1.0, 0.3, 64, 16), 3),
+])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_generated_coupling_other_geometries(lib, mesh, order, prec):
+    xyz, tri = mesh()
+    H = h2.H2Oracle(xyz, tri, order=order, leaf=48, eta=2.0)
+    u = np.vstack([np.ones(xyz.shape[0]), rhs.normal_rhs(xyz.shape[0], 2, 7)])
+    ref = H.apply(u)
+    op = lib.Operator(xyz, tri, order=order, leaf=48, eta=2.0, precision=prec, coupling="generated")
+    assert np.all(relerr(run(op, u), ref) <= TOL[prec])
