@@ -355,10 +355,10 @@ def main():
     roof = roofline_of(st, args.precision, args.coupling, kernels, n)
     roof["traffic"] = None
     if os.path.exists(TRAFFIC_FILE):
-        rec = json.load(open(TRAFFIC_FILE))
-        if rec.get("kernel_hash") == kernel_hash() and rec.get("precision") == args.precision \
-                and rec.get("workload") == args.workload and rec.get("coupling", "stored") == args.coupling:
-            roof["traffic"] = rec.get("bytes_per_launch")
+        for rec in json.load(open(TRAFFIC_FILE))["records"]:
+            if rec.get("kernel_hash") == kernel_hash() and rec.get("precision") == args.precision \
+                    and rec.get("workload") == args.workload and rec.get("coupling") == args.coupling:
+                roof["traffic"] = rec.get("bytes_per_launch")
     b_apply = apply_alg_bytes(st, elem, n, nrhs)
     lo_ms, lo_n = breakdown["near_field"]
     b_lo = near_field_alg_bytes(st, elem, n)
