@@ -149,3 +149,16 @@ def test_film_fp32_smooth_fields(lib, film):
     err = relerr(outs["fp32"], outs["fp64"])
     print(f"film fp32 vs fp64: {np.array2string(err, precision=2)}")
     assert np.all(err <= 1e-5), err
+
+
+def test_unjittered_sphere_l8_energy(lib):
+    # the same energy check on the level-8 sphere without jitter: the jittered
+    # polyhedron is rough (jitter ~0.3 edge lengths), the smooth one is not
+    xyz, tri = cases.mesh_of(cases.MeshSpec("icosphere", 8, 0.0, 0))
+    c = cases.CASES["sphere_l8"]
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp32", coupling="generated")
+    out = run(op, xyz[:, 2])
+    vol = geometry.signed_volume(xyz, tri)
+    e = energy.demag_energy_z(xyz, tri, out[0])
+    print(f"unjittered L8: E/(V/6) - 1 = {e / (vol / 6.0) - 1.0:.3e}")
+    assert abs(e / (vol / 6.0) - 1.0) < 1e-3

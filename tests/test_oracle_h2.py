@@ -174,3 +174,20 @@ def test_sparse_input_matches_dense_input(l4_h2):
     np.testing.assert_allclose(full, cols, atol=1e-14)
     e5 = H.apply(np.eye(N)[5])
     assert np.count_nonzero(e5) > N // 2
+
+
+def test_order_sweep_smallest_passing_order_is_4(l4):
+    # H2 against the dense matrix on the 2562-node sphere for m = 2..5 (u1 = z
+    # and one N(0,1) column): geometric convergence, and m = 4 is the smallest
+    # order inside 1e-4 (measured: m = 2..7 give 9.0e-3, 9.6e-4, 9.1e-5,
+    # 1.2e-5, 2.3e-6, 3.8e-7 for u1 = z)
+    xyz, tri, M = l4
+    u = np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(xyz.shape[0], 1, 0)])
+    ref = u @ M.T
+    errs = []
+    for m in (2, 3, 4, 5):
+        H = h2.H2Oracle(xyz, tri, order=m, leaf=32, eta=2.0, cache_coupling=False)
+        out = H.apply(u)
+        errs.append(np.max(np.linalg.norm(out - ref, axis=1) / np.linalg.norm(ref, axis=1)))
+    assert all(errs[q + 1] < errs[q] / 3.0 for q in range(3)), errs
+    assert errs[1] > 1e-4 >= errs[2], errs
