@@ -58,7 +58,7 @@ def case_rhs(case, xyz):
     return rhs.normal_rhs(n, case.nrhs, 0), f"{case.nrhs} N(0,1) right-hand sides"
 
 
-def describe(case, n, n_tri, rhs_text):
+def describe(case, n, n_tri, rhs_text, dense_far_max=0, coupling="stored"):
     m = case.mesh
     if m.kind == "icosphere":
         geo = f"icosphere level {m.level}, radial jitter +-{m.jitter:g}"
@@ -66,8 +66,10 @@ def describe(case, n, n_tri, rhs_text):
         geo = f"thin-film cuboid 2000 x 2000 x 20 nm on a 5 nm grid, in-plane jitter +-{m.jitter:g} nm"
     else:
         geo = m.kind
+    rep = (f"coupling matrices {'recomputed in the apply' if coupling == 'generated' else 'stored'}"
+           + (f", admissible blocks with |t||s| <= {dense_far_max} kept exact" if dense_far_max else ""))
     return (f"{case.name}: {geo}, {n} boundary nodes, {n_tri} triangles, order {case.order}, leaf {case.leaf}, "
-            f"eta {case.eta:g}, {rhs_text}")
+            f"eta {case.eta:g}, {rhs_text}; {rep}")
 
 
 def coupling_alg_bytes(st, elem_s: int, elem_v: int) -> int:
@@ -258,7 +260,8 @@ def cpu_baseline(xyz, tri, case, nrhs: int, frac: float = 0.01, seed: int = 7) -
     }
 
 
-def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4, coupling: str = "stored") -> dict:
+def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4, coupling: str = "stored",
+                dense_far: bool = False) -> dict:
     """The serving mix: Poisson arrivals of 1..16-column requests over six resident meshes.
 
     Spheres (levels 4-7), the thin film and a torus, FP32 operators; the HBM
@@ -273,7 +276,7 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4,
     for spec, order, leaf in cases.SERVING_MESHES:
         xyz, tri = cases.mesh_of(spec)
         specs.append(serving.MeshSpec(spec.name, xyz, tri, order=order, leaf=leaf, eta=2.0, precision="fp32",
-                                      coupling=coupling))
+                                      coupling=coupling, dense_far_max=order ** 6 if dense_far else 0))
     srv = serving.Server(backend, 0, n_slots=n_slots, max_batch_rhs=64)
     for s in specs:
         srv.add_mesh(s)
@@ -297,7 +300,8 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4,
             "throughput_GDOF_s": round(st["throughput_GDOF_s"], 4), "batches": st["batches"],
             "budget_GB": round(budget / 1e9, 2), "operators_GB": round(sum(resident) / 1e9, 2),
             "slots_GB": round(srv.fixed_bytes() / 1e9, 2),
-            "slots": n_slots, "precision": "fp32", "coupling": coupling, "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
+            "slots": n_slots, "precision": "fp32", "coupling": coupling, "dense_far_max": "k^2" if dense_far else 0,
+            "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
             "reloads": sum(st["reloads"].values()), "offloads": sum(st["offloads"].values())}
 
 
@@ -342,6 +346,9 @@ def main():
     ap.add_argument("--workload", default="sphere_l8")
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
     ap.add_argument("--coupling", default=DEFAULT_COUPLING, choices=("stored", "generated"))
+    ap.add_argument("--dense-far-max", type=int, default=-1,
+                    help="admissible blocks with |t||s| <= this are stored exactly (-1: k^2, i.e. whenever "
+                         "that is cheaper than a k x k coupling matrix; 0: the plain H2 matrix)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and coupling modes")
     ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")
@@ -365,9 +372,11 @@ def main():
     d_u1 = torch.tensor(u1, device=dev)
     d_u2 = torch.empty_like(d_u1)
 
+    dense_far_max = case.order ** 6 if args.dense_far_max < 0 else args.dense_far_max
+
     def build(prec, coupling):
         return h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
-                              coupling=coupling)
+                              coupling=coupling, dense_far_max=dense_far_max)
 
     t0 = time.perf_counter()
     op = build(args.precision, args.coupling)
@@ -401,9 +410,9 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "ms_per_step_median": round(ms_median, 4),
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": describe(case, n, tri.shape[0], rhs_text),
+        "config": {"workload": describe(case, n, tri.shape[0], rhs_text, dense_far_max, args.coupling),
                    "nodes": n, "rhs": nrhs, "order": case.order, "leaf": case.leaf, "eta": case.eta,
-                   "precision": args.precision, "coupling": args.coupling},
+                   "precision": args.precision, "coupling": args.coupling, "dense_far_max": dense_far_max},
         "roofline": roof,
         # the near-field kernel is the apply's HBM-bound part in either mode
         "roofline_near_field": {"bound": "hbm", "achieved": round(b_lo / (lo_ms / max(lo_n, 1) * 1e-3) / 1e9, 1),
@@ -415,6 +424,7 @@ def main():
         "apply_alg_bytes": b_apply,
         "kernel_ms_per_apply": {k: round(v[0] / 5, 4) for k, v in breakdown.items()},
         "operator": {"clusters": st.n_clusters, "far_blocks": st.n_far, "near_blocks": st.n_near,
+                     "far_blocks_dense": st.n_far_dense, "dense_far_entries": st.dense_far_entries,
                      "coupling_bytes": st.bytes_coupling, "near_bytes": st.bytes_near,
                      "resident_bytes": st.bytes_resident, "compression": round(st.compression, 5),
                      "bytes_per_dof": round(st.bytes_resident / n, 1),
@@ -463,7 +473,7 @@ def main():
 
     if not args.no_serve:
         print("# serving the mixed request stream", file=sys.stderr, flush=True)
-        out["serving"] = serve_bench(coupling=args.coupling)
+        out["serving"] = serve_bench(coupling=args.coupling, dense_far=dense_far_max > 0)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)        # 1 GiB

@@ -72,7 +72,12 @@ typedef struct {
  * S_ts(nu, mu) = 1/(4 pi |eta^t_nu - eta^s_mu|) (Section 4: the kernel at the
  * interpolation points) inside the apply, from the FP64 difference of the box
  * centres plus the two points' offsets; the same operator without the
- * coupling bytes (FP64 and FP32 precision, order <= 5; else ENOTSUP). */
+ * coupling bytes (FP64 and FP32 precision, order <= 5; else ENOTSUP).
+ * dense_far_max >= 0: an admissible block with |t| |s| <= dense_far_max is
+ * stored as its exact entries (Section 3, like an inadmissible block) instead
+ * of through the cluster bases and a k x k coupling matrix: cheaper when
+ * |t| |s| is small against k^2, and exact.  0 keeps every admissible block
+ * low-rank (the plain H2 matrix). */
 typedef struct {
     int    order;
     int    leaf;
@@ -82,6 +87,7 @@ typedef struct {
     int    device;
     void*  stream;
     int    coupling;
+    int64_t dense_far_max;
 } h2dlp_options;
 
 #define H2DLP_COUPLING_STORED     0
@@ -95,7 +101,7 @@ typedef struct {
     int32_t order, leaf, k, precision;
     int32_t depth;              /* deepest cluster level (root = 0) */
     int64_t n_clusters, n_leaves;
-    int64_t n_far, n_near;      /* admissible blocks, inadmissible leaf blocks */
+    int64_t n_far, n_near;      /* low-rank admissible blocks, inadmissible leaf blocks */
     int64_t coupling_entries;   /* n_far * k * k */
     int64_t near_entries;       /* sum over near blocks of |t| |s| */
     int64_t nearsing_entries;   /* near-singular entries kept in FP64 (all but FP64) */
@@ -103,10 +109,12 @@ typedef struct {
     int64_t bytes_resident;     /* all device memory held by the handle */
     int64_t workspace_bytes;    /* per concurrent apply (one 16-column pass) */
     double  compression;        /* 1 - (H2 bytes)/(8 N^2), the paper's ratio r (Section 6.1) */
+    int64_t n_far_dense;        /* admissible blocks stored as exact entries (dense_far_max) */
+    int64_t dense_far_entries;  /* their entries (counted in bytes_near, not in near_entries) */
 } h2dlp_stats;
 
 /* Fill *opt with defaults: order 4, leaf 32, eta 2, FP64, alpha 0.1, device -1,
- * stream NULL, coupling STORED. */
+ * stream NULL, coupling STORED, dense_far_max 0. */
 void h2dlp_default_options(h2dlp_options* opt);
 
 /* Build the H2 operator for `mesh` (copied; the caller may free it on return).
@@ -154,7 +162,8 @@ int h2dlp_info(h2dlp_handle h, h2dlp_stats* st);
  *   perm[n_nodes]          node index of each position in cluster order
  *   clusters[n_clusters*6] begin, end, level, parent, child0, child1 (-1 = none)
  *   boxes[n_clusters*6]    lo_x, lo_y, lo_z, hi_x, hi_y, hi_z of the inflated box
- *   far[n_far*2], near[n_near*2]  (target, source) cluster pairs, sorted
+ *   far[n_far*2], near[n_near*2]  (target, source) cluster pairs, sorted;
+ *                          far lists the low-rank admissible blocks only
  * Any pointer may be NULL to skip that array. */
 int h2dlp_export_structure(h2dlp_handle h, int64_t* perm, int64_t* clusters, double* boxes,
                            int64_t* far, int64_t* near);

@@ -31,7 +31,11 @@ the library by specification only, never by code):
   Euclidean box distance; squares summed x, y, z in that order);
 * Chebyshev points of the first kind cos((2l + 1) pi/(2m)) on each box axis,
   tensor index nu = l_x + m l_y + m^2 l_z, k = m^3;
-* near blocks (inadmissible leaf pairs) hold the exact entries of K.
+* near blocks (inadmissible leaf pairs) hold the exact entries of K;
+* optionally (dense_far_max > 0) an admissible block with |t| |s| <=
+  dense_far_max entries also holds its exact entries instead of the factors
+  (the storage choice of a representation variant: with dense_far_max >= N^2
+  every block is exact and the product is the dense matrix's).
 """
 from __future__ import annotations
 
@@ -198,7 +202,7 @@ def grid_points(pts_c: np.ndarray) -> np.ndarray:
 class H2Oracle:
     """Interpolation H2 matrix of M = K + D; lazily built pieces, plain matvec."""
 
-    def __init__(self, xyz, tri, order=4, leaf=32, eta=2.0, alpha=ALPHA, cache_coupling=True):
+    def __init__(self, xyz, tri, order=4, leaf=32, eta=2.0, alpha=ALPHA, cache_coupling=True, dense_far_max=0):
         geometry.check_mesh(xyz, tri)
         if order < 1 or leaf < 1 or not eta > 0:
             raise ValueError("order >= 1, leaf >= 1 and eta > 0 required")
@@ -209,7 +213,12 @@ class H2Oracle:
         (self.perm, self.begin, self.end, self.level, self.parent,
          self.child0, self.child1) = build_cluster_tree(self.xyz, leaf)
         self.lo, self.hi = support_boxes(self.xyz, self.tri, self.perm, self.begin, self.end, alpha)
-        self.far, self.near = build_block_tree(self.lo, self.hi, self.child0, self.child1, eta)
+        far_all, self.near = build_block_tree(self.lo, self.hi, self.child0, self.child1, eta)
+        # an admissible block with |t| |s| <= dense_far_max keeps its exact
+        # entries (Section 3) instead of the interpolation factors
+        size = self.end - self.begin
+        small = size[far_all[:, 0]] * size[far_all[:, 1]] <= dense_far_max
+        self.far, self.far_dense = far_all[~small], far_all[small]
         self.pts = chebyshev_points(self.lo, self.hi, order)
         self.normals, self.areas = geometry.triangle_normals_areas(self.xyz, self.tri)
         self.inc_off, self.inc_tri, self.inc_loc = geometry.incidence(self.xyz.shape[0], self.tri)
@@ -369,7 +378,7 @@ class H2Oracle:
         return y
 
     def near_field(self, x, y):
-        for t, s in self.near:
+        for t, s in np.concatenate([self.near, self.far_dense]):
             xs = x[self.nodes(s)]
             if np.any(xs != 0.0):
                 y[self.nodes(t)] += self.K_near(t, s) @ xs
@@ -390,8 +399,11 @@ class H2Oracle:
 
     # -- sizes -------------------------------------------------------------------
     def counts(self) -> dict:
-        n_near = int(sum((self.end[t] - self.begin[t]) * (self.end[s] - self.begin[s]) for t, s in self.near))
+        size = self.end - self.begin
+        n_near = int(sum(size[t] * size[s] for t, s in self.near))
+        n_dense = int(sum(size[t] * size[s] for t, s in self.far_dense))
         return dict(N=int(self.xyz.shape[0]), clusters=int(self.n_clusters),
                     leaves=int(np.sum(self.child0 < 0)), far=int(self.far.shape[0]),
                     near=int(self.near.shape[0]), near_entries=n_near,
+                    far_dense=int(self.far_dense.shape[0]), dense_far_entries=n_dense,
                     depth=int(self.level.max()))

@@ -150,6 +150,7 @@ struct h2dlp_ctx {
     std::vector<int32_t> child0, child1, parent;
     std::vector<double> boxes;
     std::vector<double> cgeo;
+    std::vector<char> far_dense;     // per block-tree admissible block: stored as exact entries
     std::vector<LeafDesc> leaves, vleaves;
     std::vector<FarDesc> fars;
     std::vector<NearDesc> nears;
@@ -287,10 +288,21 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         h->blks_fwd.push_back(BlkDesc{off_wt, int32_t(X.size()), int32_t(X.begin)});
         off_wt += int64_t(k) * X.size();
     }
-    // coupling: one item per cluster (level order), its blocks sorted by source
+    // admissible blocks small enough to keep as exact entries (|t| |s| <= dense_far_max)
+    h->far_dense.assign(S.far.size(), 0);
+    int64_t n_far_dense = 0, dense_entries = 0;
+    for (size_t b = 0; b < S.far.size(); ++b) {
+        const int64_t e = S.cl[S.far[b].first].size() * S.cl[S.far[b].second].size();
+        if (e <= o->dense_far_max) {
+            h->far_dense[b] = 1;
+            ++n_far_dense;
+            dense_entries += e;
+        }
+    }
+    // coupling: one item per cluster (level order), its low-rank blocks sorted by source
     std::vector<std::vector<int32_t>> far_by_t(C);
     for (size_t b = 0; b < S.far.size(); ++b)
-        far_by_t[h->gid_of_pre[S.far[b].first]].push_back(h->gid_of_pre[S.far[b].second]);
+        if (!h->far_dense[b]) far_by_t[h->gid_of_pre[S.far[b].first]].push_back(h->gid_of_pre[S.far[b].second]);
     int64_t off_s = 0;
     const bool gen = o->coupling == H2DLP_COUPLING_GENERATED;
     const int kp = bf16_parts(h->prec) > 0 ? bf16s_cols(k) : coupling_cols(k);
@@ -311,8 +323,19 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         }
     }
     // leaf output: V_t (n_t x k) then the near blocks of t (sorted by source position)
+    // (an exact admissible block (t, s) enters every leaf of t, restricted to that leaf's rows)
     std::vector<std::vector<int32_t>> near_by_t(C);
     for (size_t b = 0; b < S.near.size(); ++b) near_by_t[S.near[b].first].push_back(S.near[b].second);
+    for (size_t b = 0; b < S.far.size(); ++b) {
+        if (!h->far_dense[b]) continue;
+        std::vector<int32_t> stack{S.far[b].first};
+        while (!stack.empty()) {
+            const int32_t c = stack.back();
+            stack.pop_back();
+            if (S.cl[c].leaf()) near_by_t[c].push_back(S.far[b].second);
+            else { stack.push_back(S.cl[c].child0); stack.push_back(S.cl[c].child1); }
+        }
+    }
     h->vleaves.resize(leaf_pre.size());
     int64_t off_l = 0, near_entries = 0;
     for (size_t q = 0; q < leaf_pre.size(); ++q) {
@@ -367,10 +390,12 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     st.depth = S.depth;
     st.n_clusters = C;
     st.n_leaves = h->n_leaves;
-    st.n_far = int64_t(S.far.size());
+    st.n_far = int64_t(S.far.size()) - n_far_dense;
+    st.n_far_dense = n_far_dense;
+    st.dense_far_entries = dense_entries;
     st.n_near = int64_t(S.near.size());
-    st.coupling_entries = int64_t(S.far.size()) * k * k;
-    st.near_entries = near_entries;
+    st.coupling_entries = st.n_far * k * k;
+    st.near_entries = near_entries - dense_entries;
     st.nearsing_entries = fp64 ? 0 : int64_t(S.ring_pos.size());
     st.bytes_coupling = gen ? 0 : int64_t(h->elem_s * size_t(st.coupling_entries));
     if (gen) {
@@ -547,8 +572,8 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         }
 
         // near field, diagonal and near-singular part into y64 on the side stream,
-        // overlapping the coupling products (HBM-bound there, MFMA- or HBM-bound
-        // here); forked after the latency-bound upward pass so as not to slow it
+        // beside the coupling products (HBM-bound there, MFMA-bound here);
+        // forked after the latency-bound upward pass, which it would slow
         hipEvent_t fork = nullptr, join = nullptr;
         check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "event");
         check(hipEventCreateWithFlags(&join, hipEventDisableTiming), "event");
@@ -604,6 +629,7 @@ void h2dlp_default_options(h2dlp_options* o) {
     o->device = -1;
     o->stream = nullptr;
     o->coupling = H2DLP_COUPLING_STORED;
+    o->dense_far_max = 0;
 }
 
 static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle* out) {
@@ -624,6 +650,7 @@ static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_hand
         return fail(H2DLP_ENOTSUP, "BF16X3 and BF16X6 need order <= 5 (k <= 128)");
     if (o->coupling != H2DLP_COUPLING_STORED && o->coupling != H2DLP_COUPLING_GENERATED)
         return fail(H2DLP_EINVAL, "unknown coupling mode");
+    if (o->dense_far_max < 0) return fail(H2DLP_EINVAL, "dense_far_max must be >= 0");
     if (o->coupling == H2DLP_COUPLING_GENERATED &&
         (o->order > 5 || (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32)))
         return fail(H2DLP_ENOTSUP, "generated coupling needs FP64 or FP32 and order <= 5");
@@ -753,7 +780,12 @@ int h2dlp_export_structure(h2dlp_handle hh, int64_t* perm, int64_t* clusters, do
             for (int a = 0; a < 3; ++a) { boxes[6 * c + a] = X.lo[a]; boxes[6 * c + 3 + a] = X.hi[a]; }
     }
     if (far)
-        for (size_t b = 0; b < S.far.size(); ++b) { far[2 * b] = S.far[b].first; far[2 * b + 1] = S.far[b].second; }
+        for (size_t b = 0, q = 0; b < S.far.size(); ++b)
+            if (h->far_dense.empty() || !h->far_dense[b]) {
+                far[2 * q] = S.far[b].first;
+                far[2 * q + 1] = S.far[b].second;
+                ++q;
+            }
     if (near)
         for (size_t b = 0; b < S.near.size(); ++b) { near[2 * b] = S.near[b].first; near[2 * b + 1] = S.near[b].second; }
     return H2DLP_OK;

@@ -56,13 +56,25 @@ struct Mfma<double> {
     static __device__ inline int row(int g, int v) { return g + 4 * v; }
 };
 
-// Workgroups are dealt to the 8 XCDs round-robin; give each XCD a contiguous
-// range of items (neighbouring clusters share sources in its L2).
-__device__ inline int xcd_item(int n_items) {
-    const int per = gridDim.x >> 3;
-    const int item = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8).  Items are grouped in chunks of kChunk neighbouring clusters, and
+// XCD x takes chunks x, x + 8, x + 16, ...: neighbours share sources in one
+// L2, while every XCD gets a slice of every level (the levels' costs differ
+// widely, and a contiguous range per XCD left some with several times the
+// work of others).  The grid is xcd_grid(n); items past n return at once.
+constexpr int kChunk = 16;
+
+__host__ __device__ inline unsigned xcd_grid(int n_items) {
+    return unsigned(8 * kChunk * ((n_items + 8 * kChunk - 1) / (8 * kChunk)));
+}
+
+__device__ inline int xcd_item_of(int v, int n_items) {     // v: index in the grid xcd_grid(n)
+    const int x = v & 7, j = v >> 3;
+    const int item = ((j / kChunk) * 8 + x) * kChunk + j % kChunk;
     return item < n_items ? item : -1;
 }
+
+__device__ inline int xcd_item(int n_items) { return xcd_item_of(int(blockIdx.x), n_items); }
 
 enum { EPI_STORE = 0, EPI_LEAF = 1, EPI_ADD64 = 2 };
 
@@ -177,15 +189,13 @@ __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict_
     }
 }
 
+// One item of a grouped product.  Every wave of the workgroup runs it; the
+// barriers inside are reached by all waves (waves with nothing left to store
+// leave only after the last one).
 template <typename T, int RTW, int NRG, int EPI>
-__global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogue epi) {
+__device__ inline void product_item(const ProductArgs& a, const LeafEpilogue& epi, int item, T* red) {
     typedef typename Mfma<T>::acc acc_t;
     constexpr int NBG = kWaves / NRG;
-    extern __shared__ unsigned char smem_raw[];
-    T* red = reinterpret_cast<T*>(smem_raw);
-
-    const int item = xcd_item(a.n_items);
-    if (item < 0) return;
     const ItemDesc it = a.items[item];
     // the wave index is uniform per wave: keep block descriptors and base pointers in SGPRs
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -272,6 +282,15 @@ __global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogu
         }
         epi.y64[o] = y;
     }
+}
+
+// One item per workgroup, grid xcd_grid(n).
+template <typename T, int RTW, int NRG, int EPI>
+__global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogue epi) {
+    extern __shared__ unsigned char smem_raw[];
+    T* red = reinterpret_cast<T*>(smem_raw);
+    const int item = xcd_item(a.n_items);
+    if (item >= 0) product_item<T, RTW, NRG, EPI>(a, epi, item, red);
 }
 
 // Coupling products yhat_t = sum_s S_ts xhat_s for orders with k <= 128.  Every
@@ -874,7 +893,7 @@ inline int pow2ceil(int v) {
 
 template <typename T, int EPI>
 hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nrg, hipStream_t st) {
-    const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
+    const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
     if (grid == 0) return hipSuccess;
     const int nbg = kWaves / nrg;
     size_t lds = size_t(nbg - 1) * nrg * rtw * 256 * sizeof(T);
@@ -970,7 +989,7 @@ hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows
 
 hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipStream_t st) {
     if (m < 1 || m > 5 || (prec != P_FP32 && prec != P_FP64)) return hipErrorInvalidValue;
-    const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
+    const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
     if (grid == 0) return hipSuccess;
     UnitNodes un{};
     for (int l = 0; l < m; ++l) un.o[l] = std::cos((2.0 * l + 1.0) * 3.14159265358979323846 / (2.0 * m));
@@ -996,7 +1015,7 @@ hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipS
 hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st) {
     const int rt = (k + 15) / 16;
     if (prec == P_BF16X3 || prec == P_BF16X6) {
-        const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
+        const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
         if (grid == 0) return hipSuccess;
         const size_t lds = size_t(kWaves - 1) * rt * 256 * sizeof(float);
 #define H2DLP_SPLIT_CASE(R)                                                                                  \
@@ -1020,7 +1039,7 @@ hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st
         if (rt <= 8) return hipErrorInvalidValue;
         return launch_product_store(a, prec, false, st);
     }
-    const unsigned grid = unsigned(8 * ((a.n_items + 7) / 8));
+    const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
     if (grid == 0) return hipSuccess;
     const size_t lds = size_t(kWaves - 1) * rt * 256 * (prec == P_FP64 ? 8 : 4);
 #define H2DLP_CPL(T_, RT_)                                                                              \

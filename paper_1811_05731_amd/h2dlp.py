@@ -39,7 +39,7 @@ class _Mesh(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("leaf", ctypes.c_int), ("eta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("device", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("coupling", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("coupling", ctypes.c_int), ("dense_far_max", ctypes.c_int64)]
 
 
 class _Stats(ctypes.Structure):
@@ -53,7 +53,8 @@ class _Stats(ctypes.Structure):
                 ("bytes_coupling", ctypes.c_int64), ("bytes_near", ctypes.c_int64),
                 ("bytes_bases", ctypes.c_int64), ("bytes_transfer", ctypes.c_int64),
                 ("bytes_other", ctypes.c_int64), ("bytes_resident", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64), ("compression", ctypes.c_double)]
+                ("workspace_bytes", ctypes.c_int64), ("compression", ctypes.c_double),
+                ("n_far_dense", ctypes.c_int64), ("dense_far_entries", ctypes.c_int64)]
 
 
 EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
@@ -146,6 +147,8 @@ class Stats:
     bytes_resident: int
     workspace_bytes: int
     compression: float
+    n_far_dense: int
+    dense_far_entries: int
 
 
 def _ptr(t) -> int:
@@ -160,7 +163,7 @@ class Operator:
 
     def __init__(self, xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0,
                  precision="fp64", alpha: float = 0.1, device: int = -1, stream=None, plan_only: bool = False,
-                 coupling: str = "stored"):
+                 coupling: str = "stored", dense_far_max: int = 0):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         tri = np.ascontiguousarray(tri, dtype=np.int32)
         if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3:
@@ -173,6 +176,7 @@ class Operator:
         opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         opt.stream = stream
         opt.coupling = COUPLING[coupling]
+        opt.dense_far_max = int(dense_far_max)
         h = ctypes.c_void_p()
         entry = _lib.h2dlp_plan if plan_only else _lib.h2dlp_build_ex
         _check(entry(ctypes.byref(mesh), ctypes.byref(opt), ctypes.byref(h)))
@@ -272,9 +276,10 @@ class Operator:
 
 
 def plan(xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64", alpha: float = 0.1,
-         coupling: str = "stored"):
+         coupling: str = "stored", dense_far_max: int = 0):
     """Host-only structure and byte counts (no GPU needed)."""
-    return Operator(xyz, tri, order, leaf, eta, precision, alpha, plan_only=True, coupling=coupling)
+    return Operator(xyz, tri, order, leaf, eta, precision, alpha, plan_only=True, coupling=coupling,
+                    dense_far_max=dense_far_max)
 
 
 def last_error() -> str:

@@ -39,6 +39,7 @@ class MeshSpec:
     eta: float = 2.0
     precision: str = "fp32"
     coupling: str = "stored"          # "stored" | "generated" (coupling matrices recomputed in the apply)
+    dense_far_max: int = 0            # admissible blocks with |t||s| <= this kept as exact entries
 
     @property
     def n_nodes(self) -> int:
@@ -113,12 +114,12 @@ class GpuBackend(Backend):
 
     def plan_bytes(self, spec):
         p = self.h2dlp.plan(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
-                            coupling=spec.coupling)
+                            coupling=spec.coupling, dense_far_max=spec.dense_far_max)
         return p.stats.bytes_resident, p.stats.workspace_bytes
 
     def build(self, spec):
         return self.h2dlp.Operator(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
-                                   device=self.dev_index, coupling=spec.coupling)
+                                   device=self.dev_index, coupling=spec.coupling, dense_far_max=spec.dense_far_max)
 
     def offload(self, op):
         op.offload()

@@ -128,6 +128,24 @@ def test_plan_sizes():
     assert w > 0 and r > w
 
 
+@pytest.mark.parametrize("dmax", [0, 1024, 4096])
+def test_dense_far_plan_matches_oracle(dmax):
+    xyz, tri = meshes.icosphere(4, 0.01, 0)
+    s = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, dense_far_max=dmax).stats
+    ora = h2.H2Oracle(xyz, tri, order=4, leaf=32, eta=2.0, dense_far_max=dmax)
+    c = ora.counts()
+    assert (s.n_far, s.n_far_dense, s.near_entries, s.dense_far_entries) == \
+        (c["far"], c["far_dense"], c["near_entries"], c["dense_far_entries"])
+    assert s.coupling_entries == s.n_far * 64 * 64
+    assert s.bytes_near == 8 * (s.near_entries + s.dense_far_entries)
+    st = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, dense_far_max=dmax).export_structure()
+    assert np.array_equal(st["far"], ora.far)
+    if dmax:
+        assert s.n_far_dense > 0
+    with pytest.raises(h2dlp.H2dlpError):
+        h2dlp.plan(xyz, tri, dense_far_max=-1)
+
+
 def test_build_without_gpu_reports_no_device():
     import torch
     if torch.cuda.is_available():

@@ -217,3 +217,27 @@ def test_generated_coupling_other_geometries(lib, mesh, order, prec):
     ref = H.apply(u)
     op = lib.Operator(xyz, tri, order=order, leaf=48, eta=2.0, precision=prec, coupling="generated")
     assert np.all(relerr(run(op, u), ref) <= TOL[prec])
+
+
+# admissible blocks kept as exact entries (dense_far_max)
+@pytest.mark.parametrize("coupling", ["stored", "generated"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dense_far_blocks_match_oracle(lib, sphere_l4, prec, coupling):
+    xyz, tri, H_plain, u, ref_plain = sphere_l4
+    H = h2.H2Oracle(xyz, tri, order=4, leaf=32, eta=2.0, dense_far_max=4096)
+    ref = H.apply(u)
+    op = lib.Operator(xyz, tri, order=4, leaf=32, eta=2.0, precision=prec, coupling=coupling, dense_far_max=4096)
+    assert op.stats.n_far_dense == H.counts()["far_dense"] > 0
+    out = run(op, u)
+    assert np.all(relerr(out, ref) <= TOL[prec])
+    M = dense.dense_m(xyz, tri)
+    assert np.all(relerr(out, u @ M.T) < relerr(ref_plain, u @ M.T))   # closer to the exact operator
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_every_block_dense_is_the_dense_matrix(lib, prec):
+    xyz, tri = meshes.icosphere(3, 0.01, 5)
+    op = lib.Operator(xyz, tri, order=3, leaf=16, eta=2.0, precision=prec, dense_far_max=xyz.shape[0] ** 2)
+    assert op.stats.n_far == 0 and op.stats.n_far_dense > 0
+    u = rhs.normal_rhs(xyz.shape[0], 5, 9)
+    assert np.all(relerr(run(op, u), u @ dense.dense_m(xyz, tri).T) <= TOL[prec])

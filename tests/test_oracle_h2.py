@@ -191,3 +191,27 @@ def test_order_sweep_smallest_passing_order_is_4(l4):
         errs.append(np.max(np.linalg.norm(out - ref, axis=1) / np.linalg.norm(ref, axis=1)))
     assert all(errs[q + 1] < errs[q] / 3.0 for q in range(3)), errs
     assert errs[1] > 1e-4 >= errs[2], errs
+
+
+def test_dense_far_blocks():
+    # admissible blocks kept as exact entries: the block partition is unchanged,
+    # every block exact reproduces the dense matrix, and a partial threshold
+    # only removes approximation error
+    xyz, tri = meshes.icosphere(3, 0.01, 3)
+    M = dense.dense_m(xyz, tri)
+    u = np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(xyz.shape[0], 1, 0)])
+    ref = u @ M.T
+    plain = h2.H2Oracle(xyz, tri, order=3, leaf=16, eta=2.0)
+    part = h2.H2Oracle(xyz, tri, order=3, leaf=16, eta=2.0, dense_far_max=27 * 27)
+    full = h2.H2Oracle(xyz, tri, order=3, leaf=16, eta=2.0, dense_far_max=xyz.shape[0] ** 2)
+    c0, c1 = plain.counts(), part.counts()
+    assert c1["far"] + c1["far_dense"] == c0["far"] and c1["far_dense"] > 0 and c1["far"] > 0
+    assert c1["near"] == c0["near"] and c1["near_entries"] == c0["near_entries"]
+    size = part.end - part.begin
+    assert np.all(size[part.far_dense[:, 0]] * size[part.far_dense[:, 1]] <= 27 * 27)
+    assert np.all(size[part.far[:, 0]] * size[part.far[:, 1]] > 27 * 27)
+    assert full.far.shape[0] == 0
+    np.testing.assert_allclose(full.apply(u), ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    e0 = np.linalg.norm(plain.apply(u) - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    e1 = np.linalg.norm(part.apply(u) - ref, axis=1) / np.linalg.norm(ref, axis=1)
+    assert np.all(e1 < e0), (e0, e1)
