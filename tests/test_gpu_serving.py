@@ -78,6 +78,7 @@ def test_mix_equals_alone_under_budget(mods):
     srv.prewarm()
     g = np.random.default_rng(4)
     t = np.cumsum(g.exponential(1 / 400.0, 60))
+    t[:15] = 0.0                    # a burst: queued requests of one mesh must share applies
     names = list(ms)
     reqs = []
     for q in range(60):
