@@ -571,16 +571,16 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
             rec_end(h, s, 2, ev);
         }
 
+        ProductArgs nearp{h->d_items_near, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
+        LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
         // near field, diagonal and near-singular part into y64 on the side stream,
-        // beside the coupling products (HBM-bound there, MFMA-bound here);
-        // forked after the latency-bound upward pass, which it would slow
+        // beside the coupling products (HBM-bound there, MFMA- or HBM-bound
+        // here); forked after the latency-bound upward pass, which it would slow
         hipEvent_t fork = nullptr, join = nullptr;
         check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "event");
         check(hipEventCreateWithFlags(&join, hipEventDisableTiming), "event");
         check(hipEventRecord(fork, s), "event record");
         check(hipStreamWaitEvent(h->side, fork, 0), "fork");
-        ProductArgs nearp{h->d_items_near, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
-        LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
         rec_begin(h, h->side, 6, &ev);
         check(launch_product_leaf(nearp, epi, prec, h->side), "near field");
         rec_end(h, h->side, 6, ev);

@@ -85,10 +85,10 @@ __device__ inline V ld(const unsigned char* base, unsigned byte_off) {
 
 // Accumulate sum_b A_b X_b of one item into acc[RTW] (row tiles rg*RTW ...).
 //
-// A wave walks its blocks (every nbg-th of the item) as a flat sequence of
-// units -- each 16-column group of a block, then one unit for the block's tail
-// of K - 16 G columns (up to 4 k-steps loaded together) -- with the next unit's
-// loads in flight while the current unit's MFMAs run.  A unit is RTW vectors of
+// The item's blocks form a flat sequence of units -- each 16-column group of a
+// block, then one unit for the block's tail of K - 16 G columns (up to 4
+// k-steps loaded together); a wave walks every nbg-th unit with the next
+// unit's loads in flight while the current unit's MFMAs run.  A unit is RTW vectors of
 // 4 A entries (one per k-step u) and 4 B entries.  Each lane keeps, per row
 // tile, the byte offset of its group vector; lanes outside a partial tile read
 // the chunk start and discard it; tiles past the item's rows multiply zeros.
@@ -152,21 +152,27 @@ __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict_
             for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[r][u] : T(0), bv[u], acc[r]);
     };
 
-    int b = it.blk_begin + bg;
-    if (b >= it.blk_end) return;
-    BlkDesc d = blks[b];
-    int units = (d.k >> 4) + ((d.k & 15) != 0);
-    int g = 0;
-    auto advance = [&]() {
-        if (++g == units) {
-            g = 0;
-            b += nbg;
-            if (b < it.blk_end) {
-                d = blks[b];
-                units = (d.k >> 4) + ((d.k & 15) != 0);
-            }
+    // the item's units (every 16-column group of every block, then the block's
+    // tail) form one sequence; the wave takes units bg, bg + nbg, bg + 2 nbg, ...
+    // so blocks of very different widths still split evenly
+    int b = it.blk_begin, g = bg;
+    BlkDesc d{};
+    int units = 0;
+    auto settle = [&]() {                          // move (b, g) onto an existing unit
+        while (b < it.blk_end) {
+            d = blks[b];
+            units = (d.k >> 4) + ((d.k & 15) != 0);
+            if (g < units) return;
+            g -= units;
+            ++b;
         }
     };
+    auto advance = [&]() {
+        g += nbg;
+        if (g >= units) settle();
+    };
+    settle();
+    if (b >= it.blk_end) return;
     vec4 a0[RTW], a1[RTW];
     T b0[4], b1[4];
     load_unit(d, g, a0, b0);
@@ -439,23 +445,18 @@ __device__ inline double rsqrt_kernel<double>(double d2) {
 // every block, so each wave keeps a quarter of the accumulators and stores its
 // rows itself.
 template <typename T, int M, bool ROWS>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H2DLP_GEN_WAVES)))
-k_coupling_gen(ProductArgs a, UnitNodes un) {
+__device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& un, int item, T* red) {
     typedef typename Mfma<T>::acc acc_t;
     constexpr int K = M * M * M, MM = M * M, RTA = (K + 15) / 16;
     static_assert(!ROWS || RTA % kWaves == 0, "row split needs a multiple of 4 row tiles");
     constexpr int RT = ROWS ? RTA / kWaves : RTA;    // row tiles of this wave
     constexpr int Q = M / 4, R = M % 4;
     constexpr int KS_TAIL = (R * MM + 3) / 4;
-    extern __shared__ unsigned char smem_raw[];
-    T* red = reinterpret_cast<T*>(smem_raw);
     // the nodes, and the target rows' offsets h_t o_nu from the box centre
     // (the same for the 4 waves: all work on one target cluster)
     __shared__ T su[8];
     __shared__ T sot[3][16 * RTA];
 
-    const int item = xcd_item(a.n_items);
-    if (item < 0) return;
     const ItemDesc it = a.items[item];
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned lane = threadIdx.x & 63;
@@ -631,6 +632,14 @@ k_coupling_gen(ProductArgs a, UnitNodes un) {
             const int row = 16 * r + Mfma<T>::row(g, v);
             if (row < K) static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + i] = acc[r][v] * scale;
         }
+}
+
+template <typename T, int M, bool ROWS>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(H2DLP_GEN_WAVES)))
+k_coupling_gen(ProductArgs a, UnitNodes un) {
+    extern __shared__ unsigned char smem_raw[];
+    const int item = xcd_item(a.n_items);
+    if (item >= 0) coupling_gen_item<T, M, ROWS>(a, un, item, reinterpret_cast<T*>(smem_raw));
 }
 
 // Split-bfloat16 coupling products (k <= 128).  S_ts is pre-split at build time
