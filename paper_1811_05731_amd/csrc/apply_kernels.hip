@@ -806,10 +806,14 @@ __global__ void __launch_bounds__(256) k_unpermute(const double* __restrict__ y6
 // slab in LDS (index nu = lx + m ly + m^2 lz, columns innermost), one thread
 // per line of M values along the axis:
 //   UP: out[l] = sum_l' E[l'][l] in[l']  (E^T)     else  out[l'] = sum_l E[l'][l] in[l]
-template <typename T, int M, int QC, int AXIS, bool UP, bool ADD>
-__device__ inline void mode_product(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ e) {
+// One mode product of a Kronecker transfer on a k x QC slab in LDS, done by
+// `nt` threads starting at `t0`: along AXIS, out = E^T in (UP) or E in
+// (out += ... with ADD).
+template <typename T, int M, int QC, int AXIS, bool UP, bool ADD = false>
+__device__ inline void mode_product(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ e, int t0,
+                                    int nt) {
     constexpr int STRIDE = AXIS == 0 ? 1 : (AXIS == 1 ? M : M * M);
-    for (int line = threadIdx.x; line < M * M * QC; line += blockDim.x) {
+    for (int line = int(threadIdx.x) - t0; line < M * M * QC; line += nt) {
         const int q = line % QC, rest = line / QC;
         const int j1 = rest % M, j2 = rest / M;
         const int base = AXIS == 0 ? M * j1 + M * M * j2 : (AXIS == 1 ? j1 + M * M * j2 : j1 + M * j2);
@@ -827,6 +831,7 @@ __device__ inline void mode_product(const T* __restrict__ in, T* __restrict__ ou
     }
 }
 
+// columns per slab: three k x QC slabs must fit in 48 KB of LDS
 template <typename T, int M>
 constexpr int transfer_qc() {
     int qc = RHS_TILE;
@@ -834,6 +839,8 @@ constexpr int transfer_qc() {
     return qc;
 }
 
+// Upward transfer of one level: xhat_t = E_c0^T xhat_c0 + E_c1^T xhat_c1 per
+// workgroup, one child after the other through its three mode products.
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_upward(int32_t c_begin, const int32_t* __restrict__ child0,
                                                 const int32_t* __restrict__ child1, const T* __restrict__ efac,
@@ -848,6 +855,7 @@ __global__ void __launch_bounds__(256) k_upward(int32_t c_begin, const int32_t* 
         const int w = idx / (3 * MM), r = idx % (3 * MM);
         e[w][r / MM][r % MM] = efac[int64_t(ch[w]) * 3 * MM + r];
     }
+    const int nt = int(blockDim.x);
     for (int q0 = 0; q0 < RHS_TILE; q0 += QC) {
 #pragma unroll
         for (int w = 0; w < 2; ++w) {
@@ -855,12 +863,12 @@ __global__ void __launch_bounds__(256) k_upward(int32_t c_begin, const int32_t* 
             const T* src = xh + int64_t(ch[w]) * K * RHS_TILE + q0;
             for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) b0[idx] = src[(idx / QC) * RHS_TILE + idx % QC];
             __syncthreads();
-            mode_product<T, M, QC, 2, true, false>(b0, b1, e[w][2]);
+            mode_product<T, M, QC, 2, true>(b0, b1, e[w][2], 0, nt);
             __syncthreads();
-            mode_product<T, M, QC, 1, true, false>(b1, b0, e[w][1]);
+            mode_product<T, M, QC, 1, true>(b1, b0, e[w][1], 0, nt);
             __syncthreads();
-            if (w == 0) mode_product<T, M, QC, 0, true, false>(b0, acc, e[w][0]);
-            else mode_product<T, M, QC, 0, true, true>(b0, acc, e[w][0]);
+            if (w == 0) mode_product<T, M, QC, 0, true>(b0, acc, e[w][0], 0, nt);
+            else mode_product<T, M, QC, 0, true, true>(b0, acc, e[w][0], 0, nt);
         }
         __syncthreads();
         T* dst = xh + int64_t(c) * K * RHS_TILE + q0;
@@ -868,29 +876,36 @@ __global__ void __launch_bounds__(256) k_upward(int32_t c_begin, const int32_t* 
     }
 }
 
+// Downward transfer of one level: yhat_c += E_c yhat_parent per workgroup; the
+// parent's and the child's slabs come in with one round trip.
 template <typename T, int M>
 __global__ void __launch_bounds__(256) k_downward(int32_t c_begin, const int32_t* __restrict__ parent,
                                                   const T* __restrict__ efac, T* __restrict__ yh) {
     constexpr int K = M * M * M, QC = transfer_qc<T, M>(), MM = M * M;
     __shared__ T e[3][MM];
-    __shared__ T b0[K * QC], b1[K * QC];
+    __shared__ T b0[K * QC], b1[K * QC], own[K * QC];
     const int32_t c = c_begin + blockIdx.x;
     const int32_t p = parent[c];
     if (p < 0) return;
     for (int idx = threadIdx.x; idx < 3 * MM; idx += blockDim.x) e[idx / MM][idx % MM] = efac[int64_t(c) * 3 * MM + idx];
+    T* dst = yh + int64_t(c) * K * RHS_TILE;
+    const T* src = yh + int64_t(p) * K * RHS_TILE;
     for (int q0 = 0; q0 < RHS_TILE; q0 += QC) {
+        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) {
+            const int64_t o = (idx / QC) * RHS_TILE + q0 + idx % QC;
+            b0[idx] = src[o];
+            own[idx] = dst[o];
+        }
         __syncthreads();
-        const T* src = yh + int64_t(p) * K * RHS_TILE + q0;
-        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) b0[idx] = src[(idx / QC) * RHS_TILE + idx % QC];
+        mode_product<T, M, QC, 2, false>(b0, b1, e[2], 0, int(blockDim.x));
         __syncthreads();
-        mode_product<T, M, QC, 2, false, false>(b0, b1, e[2]);
+        mode_product<T, M, QC, 1, false>(b1, b0, e[1], 0, int(blockDim.x));
         __syncthreads();
-        mode_product<T, M, QC, 1, false, false>(b1, b0, e[1]);
+        mode_product<T, M, QC, 0, false>(b0, b1, e[0], 0, int(blockDim.x));
         __syncthreads();
-        mode_product<T, M, QC, 0, false, false>(b0, b1, e[0]);
+        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x)
+            dst[(idx / QC) * RHS_TILE + q0 + idx % QC] = own[idx] + b1[idx];
         __syncthreads();
-        T* dst = yh + int64_t(c) * K * RHS_TILE + q0;
-        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) dst[(idx / QC) * RHS_TILE + idx % QC] += b1[idx];
     }
 }
 
@@ -1003,7 +1018,8 @@ hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipS
     UnitNodes un{};
     for (int l = 0; l < m; ++l) un.o[l] = std::cos((2.0 * l + 1.0) * 3.14159265358979323846 / (2.0 * m));
     const int rt = (m * m * m + 15) / 16;
-    const size_t lds = size_t(kWaves - 1) * rt * 256 * (prec == P_FP64 ? 8 : 4);
+    // orders 4 and 5 split rows over waves (no LDS reduction); lower orders split blocks
+    const size_t lds = m >= 4 ? 0 : size_t(kWaves - 1) * rt * 256 * (prec == P_FP64 ? 8 : 4);
 #define H2DLP_GEN_LAUNCH(MM, ROWS)                                                                              \
     if (prec == P_FP64)                                                                                         \
         hipLaunchKernelGGL((k_coupling_gen<double, MM, ROWS>), dim3(grid), dim3(kThreads), lds, st, a, un);    \
