@@ -162,3 +162,20 @@ def test_unjittered_sphere_l8_energy(lib):
     e = energy.demag_energy_z(xyz, tri, out[0])
     print(f"unjittered L8: E/(V/6) - 1 = {e / (vol / 6.0) - 1.0:.3e}")
     assert abs(e / (vol / 6.0) - 1.0) < 1e-3
+
+
+def test_sphere_l8_bench_configuration(lib, sphere_l8):
+    # the configuration bench.py times: generated coupling, admissible blocks
+    # with |t||s| <= k^2 kept exact, FP32; sampled unit columns against the
+    # oracle built with the same block choice
+    c, xyz, tri = sphere_l8
+    dmax = (c.order ** 3) ** 2
+    H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False, dense_far_max=dmax)
+    u = unit_columns(xyz.shape[0], 16, 14)
+    ref = H.apply(u)
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp32", coupling="generated",
+                      dense_far_max=dmax)
+    assert op.stats.n_far_dense == H.counts()["far_dense"]
+    err = relerr(run(op, u), ref)
+    print(f"bench configuration vs oracle: {np.array2string(err, precision=2)}")
+    assert np.all(err <= 1e-6), err
