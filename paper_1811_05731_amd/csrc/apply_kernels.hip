@@ -433,9 +433,6 @@ __device__ inline double rsqrt_kernel<double>(double d2) {
     return y;
 }
 
-#ifndef H2DLP_GEN_PREFETCH
-#define H2DLP_GEN_PREFETCH 1   // FP32: load the next block's xhat rows during this block
-#endif
 #ifndef H2DLP_GEN_WAVES
 #define H2DLP_GEN_WAVES 2      // minimum waves per SIMD the register allocation must allow
 #endif
@@ -576,25 +573,13 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
         }
     };
 
-    if constexpr (sizeof(T) == 4 && H2DLP_GEN_PREFETCH) {
-        // FP32: the next block's B values are in flight while this block runs
-        T b0[NB], b1[NB];
-        int b = first;
-        if (b < it.blk_end) load_b(b, b0);
-        for (; b < it.blk_end; b += 2 * stride) {
-            const bool more = b + stride < it.blk_end;
-            if (more) load_b(b + stride, b1);
-            block(b, b0);
-            if (!more) break;
-            if (b + 2 * stride < it.blk_end) load_b(b + 2 * stride, b0);
-            block(b + stride, b1);
-        }
-    } else {
-        T b0[NB];
-        for (int b = first; b < it.blk_end; b += stride) {
-            load_b(b, b0);
-            block(b, b0);
-        }
+    // one block at a time: holding the next block's B values as well would cost
+    // registers, and a fourth wave per SIMD hides the load latency better
+    // (measured 1.9 against 2.9 ms at L8 beside the near field)
+    T b0[NB];
+    for (int b = first; b < it.blk_end; b += stride) {
+        load_b(b, b0);
+        block(b, b0);
     }
 
     const T scale = T(0.25 / 3.14159265358979323846);
