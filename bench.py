@@ -46,6 +46,20 @@ def workload(name: str):
     return c, xyz, tri
 
 
+def default_dense_far_max(order: int, coupling: str) -> int:
+    """Largest |t||s| for which an admissible block is cheaper kept exact.
+
+    Stored coupling: whenever its entries are fewer than the k^2 of a coupling
+    matrix (bytes against bytes).  Generated coupling: the exact block costs
+    4 |t||s| bytes of HBM (~5 TB/s achieved) while the low-rank block costs
+    2 k^2 16 flops of FP32 MFMA (~92 TFLOP/s achieved); they balance at
+    |t||s| ~ 0.43 k^2, taken as 2 k^2 / 5 (the measured optimum at L8 lies
+    between 0.39 and 0.52 k^2).
+    """
+    k2 = order ** 6
+    return k2 if coupling == "stored" else (2 * k2) // 5
+
+
 def case_rhs(case, xyz):
     """The right-hand sides each workload is quoted with, and their description."""
     from workloads import rhs
@@ -360,8 +374,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"))
     ap.add_argument("--coupling", default=DEFAULT_COUPLING, choices=("stored", "generated"))
     ap.add_argument("--dense-far-max", type=int, default=-1,
-                    help="admissible blocks with |t||s| <= this are stored exactly (-1: k^2, i.e. whenever "
-                         "that is cheaper than a k x k coupling matrix; 0: the plain H2 matrix)")
+                    help="admissible blocks with |t||s| <= this are stored exactly (0: the plain H2 matrix; "
+                         "-1: where that is cheaper -- k^2 with stored coupling, 2k^2/5 with generated coupling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and coupling modes")
     ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")
@@ -385,7 +399,7 @@ def main():
     d_u1 = torch.tensor(u1, device=dev)
     d_u2 = torch.empty_like(d_u1)
 
-    dense_far_max = case.order ** 6 if args.dense_far_max < 0 else args.dense_far_max
+    dense_far_max = args.dense_far_max if args.dense_far_max >= 0 else default_dense_far_max(case.order, args.coupling)
 
     def build(prec, coupling):
         return h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
