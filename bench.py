@@ -401,9 +401,12 @@ def main():
 
     dense_far_max = args.dense_far_max if args.dense_far_max >= 0 else default_dense_far_max(case.order, args.coupling)
 
+    def dmax_of(coupling):
+        return args.dense_far_max if args.dense_far_max >= 0 else default_dense_far_max(case.order, coupling)
+
     def build(prec, coupling):
         return h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
-                              coupling=coupling, dense_far_max=dense_far_max)
+                              coupling=coupling, dense_far_max=dmax_of(coupling))
 
     t0 = time.perf_counter()
     op = build(args.precision, args.coupling)
@@ -482,6 +485,7 @@ def main():
             outs[key] = d_u2.cpu().numpy()
             ev = 8 if prec == "fp64" else 4
             variants[key] = {"value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
+                             "dense_far_max": dmax_of(cpl),
                              "coupling": roofline_of(opv.stats, prec, cpl, kv, n),
                              "resident_GB": round(opv.stats.bytes_resident / 1e9, 2),
                              "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9

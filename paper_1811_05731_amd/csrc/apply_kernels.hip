@@ -83,32 +83,33 @@ __device__ inline V ld(const unsigned char* base, unsigned byte_off) {
     return *reinterpret_cast<const V*>(base + byte_off);   // SGPR base + 32-bit VGPR offset
 }
 
-// Accumulate sum_b A_b X_b of one item into acc[RTW] (row tiles rg*RTW ...).
+// Accumulate sum_b A_b X_b of one item into acc[RTW] (row tiles t0 ... t0 + RTW - 1,
+// all of them holding rows of the item).
 //
 // The item's blocks form a flat sequence of units -- each 16-column group of a
 // block, then one unit for the block's tail of K - 16 G columns (up to 4
 // k-steps loaded together); a wave walks every nbg-th unit with the next
 // unit's loads in flight while the current unit's MFMAs run.  A unit is RTW vectors of
 // 4 A entries (one per k-step u) and 4 B entries.  Each lane keeps, per row
-// tile, the byte offset of its group vector; lanes outside a partial tile read
-// the chunk start and discard it; tiles past the item's rows multiply zeros.
+// tile, the byte offset of its group vector; lanes past the rows of a partial
+// tile read the group's first entries (finite values) and so only fill
+// result rows past the item, which are never stored.
 template <typename T, int RTW>
 __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict__ blks, const T* __restrict__ pool,
-                                  const T* __restrict__ x0, const T* __restrict__ x1, int rg, int bg, int nbg,
+                                  const T* __restrict__ x0, const T* __restrict__ x1, int t0, int bg, int nbg,
                                   typename Mfma<T>::acc* acc) {
     typedef typename Mfma<T>::vec4 vec4;
     constexpr unsigned E = sizeof(T);
     const unsigned lane = threadIdx.x & 63;
     const unsigned i = lane & 15, kk = lane >> 4;
     const int M = it.m;
-    const int RT = (M + 15) >> 4;
     unsigned goff[RTW], rvs[RTW];
     bool ok[RTW];
 #pragma unroll
     for (int r = 0; r < RTW; ++r) {
-        const int rt = rg * RTW + r;
+        const int rt = t0 + r;
         rvs[r] = unsigned(M - 16 * rt < 16 ? M - 16 * rt : 16);
-        ok[r] = rt < RT && i < rvs[r];
+        ok[r] = i < rvs[r];
         goff[r] = ok[r] ? E * (256u * rt + 4u * (kk * rvs[r] + i)) : 0u;
     }
     const unsigned xoff = E * lane;
@@ -137,7 +138,7 @@ __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict_
                 bv[u] = kk < kv ? bl : T(0);
 #pragma unroll
                 for (int r = 0; r < RTW; ++r) {
-                    const unsigned rt = unsigned(rg * RTW + r);
+                    const unsigned rt = unsigned(t0 + r);
                     const bool valid = ok[r] && kk < kv;
                     const T al = ld<T>(At, valid ? E * (4u * M * u + 16u * rt * kv + kk * rvs[r] + i) : 0u);
                     av[r][u] = valid ? al : T(0);
@@ -149,7 +150,7 @@ __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict_
 #pragma unroll
         for (int u = 0; u < 4; ++u)
 #pragma unroll
-            for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(ok[r] ? av[r][u] : T(0), bv[u], acc[r]);
+            for (int r = 0; r < RTW; ++r) acc[r] = Mfma<T>::mma(av[r][u], bv[u], acc[r]);
     };
 
     // the item's units (every 16-column group of every block, then the block's
@@ -195,6 +196,22 @@ __device__ inline void accumulate(const ItemDesc& it, const BlkDesc* __restrict_
     }
 }
 
+// accumulate over the wave's row tiles that hold rows of the item (live of
+// RTW; uniform per wave): a leaf of 40 rows takes 3 tiles, not 4, and the
+// dead tiles cost neither loads nor MFMAs.
+template <typename T, int NR>
+__device__ inline void accumulate_live(int live, const ItemDesc& it, const BlkDesc* __restrict__ blks,
+                                       const T* __restrict__ pool, const T* __restrict__ x0, const T* __restrict__ x1,
+                                       int t0, int bg, int nbg, typename Mfma<T>::acc* acc) {
+    if constexpr (NR > 0) {
+        if (live >= NR) {
+            accumulate<T, NR>(it, blks, pool, x0, x1, t0, bg, nbg, acc);
+            return;
+        }
+        accumulate_live<T, NR - 1>(live, it, blks, pool, x0, x1, t0, bg, nbg, acc);
+    }
+}
+
 // One item of a grouped product.  Every wave of the workgroup runs it; the
 // barriers inside are reached by all waves (waves with nothing left to store
 // leave only after the last one).
@@ -211,8 +228,9 @@ __device__ inline void product_item(const ProductArgs& a, const LeafEpilogue& ep
     acc_t acc[RTW];
 #pragma unroll
     for (int r = 0; r < RTW; ++r) acc[r] = acc_t{0, 0, 0, 0};
-    accumulate<T, RTW>(it, a.blks, static_cast<const T*>(a.pool), static_cast<const T*>(a.x0),
-                       static_cast<const T*>(a.x1), rg, bg, NBG, acc);
+    const int live = __builtin_amdgcn_readfirstlane(((it.m + 15) >> 4) - rg * RTW);
+    accumulate_live<T, RTW>(live, it, a.blks, static_cast<const T*>(a.pool), static_cast<const T*>(a.x0),
+                            static_cast<const T*>(a.x1), rg * RTW, bg, NBG, acc);
 
     if (NBG > 1) {   // fixed-order reduction of the block groups
         if (bg > 0) {
@@ -414,6 +432,11 @@ __global__ void __launch_bounds__(kThreads) k_coupling(ProductArgs a, int kvalid
 // tables; the remaining mu_x (m mod 4 values, all m^2 pairs) form a tail of
 // k-steps with per-lane columns.  FP32 uses v_rsq_f32 and FP64 refines v_rsq_f64
 // with two Newton steps.
+//
+// Padding takes no masks: a row past K (its offset is that of node 0) only
+// feeds an output row that is never stored, and a tail column past the block
+// (again a real node's offset) meets a zero B value; both distances are
+// between two separated boxes, so every entry is finite.
 struct UnitNodes {
     double o[8];
 };
@@ -551,8 +574,7 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
                         const T ey = ay[r] - hsy * u[p % M], ez = az[r] - hsz * u[p / M];
                         d2 = dx2[r] + ey * ey + ez * ez;
                     }
-                    const T sv = 16 * (r0 + r) + i < K ? rsqrt_kernel<T>(d2) : T(0);
-                    acc[r] = Mfma<T>::mma(sv, bv[q * MM + p], acc[r]);
+                    acc[r] = Mfma<T>::mma(rsqrt_kernel<T>(d2), bv[q * MM + p], acc[r]);
                 }
             }
         }
@@ -567,8 +589,7 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
             for (int r = 0; r < RT; ++r) {
                 const T ex = ax[r] - osx, ey = ay[r] - osy, ez = az[r] - osz;
                 const T d2 = ex * ex + ey * ey + ez * ez;
-                const T sv = ok && 16 * (r0 + r) + i < K ? rsqrt_kernel<T>(d2) : T(0);
-                acc[r] = Mfma<T>::mma(sv, bv[Q * MM + ts], acc[r]);
+                acc[r] = Mfma<T>::mma(rsqrt_kernel<T>(d2), bv[Q * MM + ts], acc[r]);
             }
         }
     };
