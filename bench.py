@@ -52,12 +52,12 @@ def default_dense_far_max(order: int, coupling: str) -> int:
     Stored coupling: whenever its entries are fewer than the k^2 of a coupling
     matrix (bytes against bytes).  Generated coupling: the exact block costs
     4 |t||s| bytes of HBM (~5 TB/s achieved) while the low-rank block costs
-    2 k^2 16 flops of FP32 MFMA (~92 TFLOP/s achieved); they balance at
-    |t||s| ~ 0.43 k^2, taken as 2 k^2 / 5 (the measured optimum at L8 lies
-    between 0.39 and 0.52 k^2).
+    2 k^2 16 flops of FP32 MFMA (~92 TFLOP/s achieved); alone they would
+    balance at |t||s| ~ 0.43 k^2.  The two run side by side, and at L8 the
+    apply time is flat within 1 % from 0.5 to 0.63 k^2: k^2 / 2 is taken.
     """
     k2 = order ** 6
-    return k2 if coupling == "stored" else (2 * k2) // 5
+    return k2 if coupling == "stored" else k2 // 2
 
 
 def case_rhs(case, xyz):
@@ -375,7 +375,7 @@ def main():
     ap.add_argument("--coupling", default=DEFAULT_COUPLING, choices=("stored", "generated"))
     ap.add_argument("--dense-far-max", type=int, default=-1,
                     help="admissible blocks with |t||s| <= this are stored exactly (0: the plain H2 matrix; "
-                         "-1: where that is cheaper -- k^2 with stored coupling, 2k^2/5 with generated coupling)")
+                         "-1: where that is cheaper -- k^2 with stored coupling, k^2/2 with generated coupling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and coupling modes")
     ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")

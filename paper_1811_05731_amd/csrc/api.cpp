@@ -134,6 +134,9 @@ struct h2dlp_ctx {
     size_t ws_bytes = 0, ws_x = 0, ws_x64 = 0, ws_y64 = 0, ws_xh = 0;
     int32_t n_items_fwd = 0, n_items_cpl = 0, n_items_leaf = 0;
     int32_t rt_leaf = 1;
+    // LDS each near-field workgroup reserves: a quarter of a CU's, so that a CU
+    // holding four of them (their register limit) takes no coupling workgroup
+    size_t near_lds = 0;
     int kp = 0;                      // stored columns of a coupling block
     bool materialized = false;
     // offload: device buffers parked in pinned host memory
@@ -454,6 +457,13 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_items_near = h->upload(h->items_near, &kept, stream);
     h->d_items_v = h->upload(h->items_v, &kept, stream);
     check(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "side stream");
+    {
+        int dev = 0, lds_cu = 0, lds_wg = 0;
+        check(hipGetDevice(&dev), "device");
+        check(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev), "attribute");
+        check(hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
+        h->near_lds = size_t(std::max(0, std::min(lds_cu / 4, lds_wg)));
+    }
     if (!fp64) {
         h->d_ns_off = h->upload(S.ring_off, &kept, stream);
         h->d_ns_pos = h->upload(S.ring_pos, &kept, stream);
@@ -582,7 +592,7 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         check(hipEventRecord(fork, s), "event record");
         check(hipStreamWaitEvent(h->side, fork, 0), "fork");
         rec_begin(h, h->side, 6, &ev);
-        check(launch_product_leaf(nearp, epi, prec, h->side), "near field");
+        check(launch_product_leaf(nearp, epi, prec, h->n_items_cpl > 0 ? h->near_lds : 0, h->side), "near field");
         rec_end(h, h->side, 6, ev);
         check(hipEventRecord(join, h->side), "event record");
 

@@ -19,6 +19,7 @@
 // registers, four k-steps per lane load (layout.h); X rows come through L2.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "kernels.h"
@@ -922,12 +923,14 @@ inline int pow2ceil(int v) {
 }
 
 template <typename T, int EPI>
-hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nrg, hipStream_t st) {
+hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nrg, hipStream_t st,
+                    size_t lds_floor = 0) {
     const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
     if (grid == 0) return hipSuccess;
     const int nbg = kWaves / nrg;
     size_t lds = size_t(nbg - 1) * nrg * rtw * 256 * sizeof(T);
     if (EPI == EPI_LEAF) lds += size_t(16 * rtw) * RHS_TILE * sizeof(T);   // staged output rows
+    lds = std::max(lds, lds_floor);
 #define H2DLP_CASE(RTW_, NRG_)                                                                       \
     if (rtw == RTW_ && nrg == NRG_) {                                                                \
         hipLaunchKernelGGL((k_product<T, RTW_, NRG_, EPI>), dim3(grid), dim3(kThreads), lds, st, a, e); \
@@ -1098,11 +1101,12 @@ hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hip
     return dispatch<float, EPI_ADD64>(a, e, rtw, nrg, st);
 }
 
-hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st) {
+hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, size_t lds_floor,
+                               hipStream_t st) {
     const int rtw = pow2ceil(a.rt);
     if (rtw > 8) return hipErrorInvalidValue;
-    if (prec == P_FP64) return dispatch<double, EPI_LEAF>(a, e, rtw, 1, st);
-    return dispatch<float, EPI_LEAF>(a, e, rtw, 1, st);
+    if (prec == P_FP64) return dispatch<double, EPI_LEAF>(a, e, rtw, 1, st, lds_floor);
+    return dispatch<float, EPI_LEAF>(a, e, rtw, 1, st, lds_floor);
 }
 
 hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, const int32_t* child1, const void* e,

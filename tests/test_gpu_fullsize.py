@@ -166,10 +166,10 @@ def test_unjittered_sphere_l8_energy(lib):
 
 def test_sphere_l8_bench_configuration(lib, sphere_l8):
     # the configuration bench.py times: generated coupling, admissible blocks
-    # with |t||s| <= 2k^2/5 kept exact, FP32; sampled unit columns against the
+    # with |t||s| <= k^2/2 kept exact, FP32; sampled unit columns against the
     # oracle built with the same block choice
     c, xyz, tri = sphere_l8
-    dmax = 2 * (c.order ** 3) ** 2 // 5
+    dmax = (c.order ** 3) ** 2 // 2
     H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False, dense_far_max=dmax)
     u = unit_columns(xyz.shape[0], 16, 14)
     ref = H.apply(u)
