@@ -114,6 +114,7 @@ struct h2dlp_ctx {
     int32_t* d_child0 = nullptr;
     int32_t* d_child1 = nullptr;
     int32_t* d_parent = nullptr;
+    int32_t* d_front = nullptr;
     void* d_e = nullptr;
     void* d_pool_wt = nullptr;
     void* d_pool_s = nullptr;
@@ -151,6 +152,11 @@ struct h2dlp_ctx {
     std::vector<Parked> parked;
     // host-side plan
     std::vector<int32_t> child0, child1, parent;
+    // downward pass: the clusters of level down_l0 and the leaves above it get
+    // their yhat in one launch, each from its path to the root; the levels
+    // below follow one launch per level
+    std::vector<int32_t> down_front;
+    int32_t down_l0 = 0;
     std::vector<double> boxes;
     std::vector<double> cgeo;
     std::vector<char> far_dense;     // per block-tree admissible block: stored as exact entries
@@ -185,6 +191,7 @@ struct h2dlp_ctx {
     std::vector<std::pair<void**, bool>> fields() {
         return {{(void**)&d_perm, false}, {(void**)&d_iperm, false}, {(void**)&d_diag, false},
                 {(void**)&d_child0, false}, {(void**)&d_child1, false}, {(void**)&d_parent, false},
+                {(void**)&d_front, false},
                 {(void**)&d_e, false}, {(void**)&d_pool_wt, false}, {(void**)&d_pool_s, false},
                 {(void**)&d_cgeo, false},
                 {(void**)&d_pool_leaf, false}, {(void**)&d_items_fwd, false}, {(void**)&d_blks_fwd, false},
@@ -274,6 +281,16 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         if (X.parent >= 0) h->parent[g] = h->gid_of_pre[X.parent];
         for (int a = 0; a < 3; ++a) { h->boxes[6 * size_t(g) + a] = X.lo[a]; h->boxes[6 * size_t(g) + 3 + a] = X.hi[a]; }
     }
+    // the deepest level down to which no level holds more than kPathFront
+    // clusters (paths of at most kMaxPath clusters), and the leaves above it
+    h->down_l0 = 0;
+    for (int l = 1; l <= S.depth && l < kMaxPath; ++l) {
+        if (h->level_off[l + 1] - h->level_off[l] > kPathFront) break;
+        h->down_l0 = l;
+    }
+    h->down_front.clear();
+    for (int32_t g = 0; g < h->level_off[h->down_l0 + 1]; ++g)
+        if (g >= h->level_off[h->down_l0] || h->child0[g] < 0) h->down_front.push_back(g);
     std::vector<int32_t> leaf_pre;
     for (int32_t g = 0; g < C; ++g)
         if (S.cl[order[g]].leaf()) leaf_pre.push_back(order[g]);
@@ -442,6 +459,7 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_child0 = h->upload(h->child0, &kept, stream);
     h->d_child1 = h->upload(h->child1, &kept, stream);
     h->d_parent = h->upload(h->parent, &kept, stream);
+    h->d_front = h->upload(h->down_front, &kept, stream);
     h->d_diag = h->alloc<double>(sizeof(double) * N, &kept);
     h->d_e = h->alloc<void>(e * size_t(C) * 3 * m * m, &kept);
     h->d_pool_wt = h->alloc<void>(e * size_t(h->off_wt), &kept);
@@ -606,7 +624,11 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         }
         rec_end(h, s, 3, ev);
 
-        for (int l = 1; l <= h->S.depth; ++l) {
+        rec_begin(h, s, 4, &ev);
+        check(launch_downward_paths(int32_t(h->down_front.size()), h->d_front, h->d_parent, h->d_e, yh, m, prec, s),
+              "downward");
+        rec_end(h, s, 4, ev);
+        for (int l = h->down_l0 + 1; l <= h->S.depth; ++l) {
             rec_begin(h, s, 4, &ev);
             check(launch_downward(h->level_off[l], h->level_off[l + 1], h->d_parent, h->d_e, yh, m, prec, s), "downward");
             rec_end(h, s, 4, ev);

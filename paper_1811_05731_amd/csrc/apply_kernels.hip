@@ -9,7 +9,7 @@
 //                  leaf output    y|_t = V_t yhat_t + sum_{s near} K_ts x|_s, then
 //                                 y64 = y + D x64 (+ FP64 near-singular part), cluster order
 //   upward       xhat_t = sum_c E_c^T xhat_c     (Kronecker mode products, per level)
-//   downward     yhat_c += E_c yhat_parent        (per level)
+//   downward     yhat_c += E_c yhat_parent        (top levels along paths, then per level)
 //   unpermute    u2 = P^T y64
 //
 // The product kernel owns every output row it writes (no atomics): a
@@ -916,6 +916,59 @@ __global__ void __launch_bounds__(256) k_downward(int32_t c_begin, const int32_t
     }
 }
 
+// Downward pass over the top levels in one launch: workgroup b takes cluster
+// d = front[b] and walks its path from the root, z = yhat_root, then
+// z = yhat_a + E_a z for each cluster a below, down to d; only yhat_d is
+// written.  The arithmetic of every step is that of k_downward, so the result
+// is the same as level by level; the clusters above the front are computed
+// once per path that passes through them instead of once (a few thousand
+// extra transfers at most) to save a launch per level.  No cluster is both
+// read and written: front clusters are at the front level or leaves, never
+// on another front cluster's path.
+template <typename T, int M>
+__global__ void __launch_bounds__(256) k_downward_paths(const int32_t* __restrict__ front,
+                                                        const int32_t* __restrict__ parent,
+                                                        const T* __restrict__ efac, T* __restrict__ yh) {
+    constexpr int K = M * M * M, QC = transfer_qc<T, M>(), MM = M * M;
+    __shared__ T e[3][MM];
+    __shared__ T b0[K * QC], b1[K * QC], own[K * QC];
+    __shared__ int32_t path[kMaxPath];
+    __shared__ int n_path;
+    const int32_t d = front[blockIdx.x];
+    if (threadIdx.x == 0) {
+        int n = 0;
+        for (int32_t c = d; c >= 0 && n < kMaxPath; c = parent[c]) path[n++] = c;
+        n_path = n;
+    }
+    __syncthreads();
+    const int n = n_path;
+    if (n < 2) return;                                 // the root: its yhat is complete
+    for (int q0 = 0; q0 < RHS_TILE; q0 += QC) {
+        const T* root = yh + int64_t(path[n - 1]) * K * RHS_TILE;
+        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) b0[idx] = root[(idx / QC) * RHS_TILE + q0 + idx % QC];
+        for (int j = n - 2; j >= 0; --j) {
+            const int32_t c = path[j];
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < 3 * MM; idx += blockDim.x)
+                e[idx / MM][idx % MM] = efac[int64_t(c) * 3 * MM + idx];
+            const T* src = yh + int64_t(c) * K * RHS_TILE;
+            for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) own[idx] = src[(idx / QC) * RHS_TILE + q0 + idx % QC];
+            __syncthreads();
+            mode_product<T, M, QC, 2, false>(b0, b1, e[2], 0, int(blockDim.x));
+            __syncthreads();
+            mode_product<T, M, QC, 1, false>(b1, b0, e[1], 0, int(blockDim.x));
+            __syncthreads();
+            mode_product<T, M, QC, 0, false>(b0, b1, e[0], 0, int(blockDim.x));
+            __syncthreads();
+            for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) b0[idx] = own[idx] + b1[idx];
+        }
+        __syncthreads();
+        T* dst = yh + int64_t(d) * K * RHS_TILE;
+        for (int idx = threadIdx.x; idx < K * QC; idx += blockDim.x) dst[(idx / QC) * RHS_TILE + q0 + idx % QC] = b0[idx];
+        __syncthreads();
+    }
+}
+
 inline int pow2ceil(int v) {
     int p = 1;
     while (p < v) p <<= 1;
@@ -1116,6 +1169,27 @@ hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, 
     if (prec == P_FP64)
         return upward_m<double>(m, grid, st, c_begin, child0, child1, static_cast<const double*>(e), static_cast<double*>(xh));
     return upward_m<float>(m, grid, st, c_begin, child0, child1, static_cast<const float*>(e), static_cast<float*>(xh));
+}
+
+hipError_t launch_downward_paths(int32_t n_front, const int32_t* front, const int32_t* parent, const void* e, void* yh,
+                                 int m, int prec, hipStream_t st) {
+    if (n_front <= 0) return hipSuccess;
+    const unsigned grid = unsigned(n_front);
+    switch (m) {
+#define H2DLP_M(MM_)                                                                                              \
+    case MM_:                                                                                                     \
+        if (prec == P_FP64)                                                                                       \
+            hipLaunchKernelGGL((k_downward_paths<double, MM_>), dim3(grid), dim3(256), 0, st, front, parent,       \
+                               static_cast<const double*>(e), static_cast<double*>(yh));                          \
+        else                                                                                                      \
+            hipLaunchKernelGGL((k_downward_paths<float, MM_>), dim3(grid), dim3(256), 0, st, front, parent,        \
+                               static_cast<const float*>(e), static_cast<float*>(yh));                            \
+        break;
+        H2DLP_M(1) H2DLP_M(2) H2DLP_M(3) H2DLP_M(4) H2DLP_M(5) H2DLP_M(6) H2DLP_M(7) H2DLP_M(8)
+#undef H2DLP_M
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_downward(int32_t c_begin, int32_t c_end, const int32_t* parent, const void* e, void* yh, int m,

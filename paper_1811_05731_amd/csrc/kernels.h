@@ -104,5 +104,13 @@ hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, 
                          void* xh, int m, int prec, hipStream_t st);
 hipError_t launch_downward(int32_t c_begin, int32_t c_end, const int32_t* parent, const void* e, void* yh, int m,
                            int prec, hipStream_t st);
+// Downward pass over the top of the tree in one launch: for each cluster d of
+// front, yhat_d = yhat_d + E_d (yhat_parent + E_parent (... yhat_root)), along
+// its path to the root (at most kMaxPath clusters).  Only the front clusters
+// are written; the clusters above them are read (their coupling part).
+constexpr int kMaxPath = 32;
+constexpr int kPathFront = 1024;
+hipError_t launch_downward_paths(int32_t n_front, const int32_t* front, const int32_t* parent, const void* e, void* yh,
+                                 int m, int prec, hipStream_t st);
 
 }  // namespace h2dlp
