@@ -135,9 +135,11 @@ struct h2dlp_ctx {
     size_t ws_bytes = 0, ws_x = 0, ws_x64 = 0, ws_y64 = 0, ws_xh = 0;
     int32_t n_items_fwd = 0, n_items_cpl = 0, n_items_leaf = 0;
     int32_t rt_leaf = 1;
-    // LDS each near-field workgroup reserves: a quarter of a CU's, so that a CU
-    // holding four of them (their register limit) takes no coupling workgroup
-    size_t near_lds = 0;
+    // LDS each FP32 generated-coupling workgroup reserves beyond its own
+    // arrays: a quarter of a CU's, so that at most three share a CU (their
+    // registers would allow six) and the near field running beside them keeps
+    // its share.  The FP64 kernel's registers already allow only four.
+    size_t cpl_lds = 0;
     int kp = 0;                      // stored columns of a coupling block
     bool materialized = false;
     // offload: device buffers parked in pinned host memory
@@ -480,7 +482,7 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
         check(hipGetDevice(&dev), "device");
         check(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev), "attribute");
         check(hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
-        h->near_lds = size_t(std::max(0, std::min(lds_cu / 4, lds_wg)));
+        h->cpl_lds = size_t(std::max(0, std::min(lds_cu / 4, lds_wg)));
     }
     if (!fp64) {
         h->d_ns_off = h->upload(S.ring_off, &kept, stream);
@@ -610,14 +612,15 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         check(hipEventRecord(fork, s), "event record");
         check(hipStreamWaitEvent(h->side, fork, 0), "fork");
         rec_begin(h, h->side, 6, &ev);
-        check(launch_product_leaf(nearp, epi, prec, h->n_items_cpl > 0 ? h->near_lds : 0, h->side), "near field");
+        check(launch_product_leaf(nearp, epi, prec, h->side), "near field");
         rec_end(h, h->side, 6, ev);
         check(hipEventRecord(join, h->side), "event record");
 
         rec_begin(h, s, 3, &ev);
         if (h->d_cgeo) {
             ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_cgeo, xh, nullptr, yh};
-            check(launch_coupling_generated(cpl, m, prec, s), "coupling");
+            check(launch_coupling_generated(cpl, m, prec, prec == P_FP32 && h->n_items_leaf > 0 ? h->cpl_lds : 0, s),
+                  "coupling");
         } else {
             ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
             check(launch_coupling(cpl, k, prec, s), "coupling");

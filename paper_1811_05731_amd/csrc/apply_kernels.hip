@@ -516,6 +516,10 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
     const int stride = ROWS ? 1 : kWaves;
     constexpr int NB = Q * MM + KS_TAIL;               // k-steps (B values) per block
     constexpr bool kTables = ROWS;                     // few row tiles per wave: per-block distance tables
+    // order 5: the tail (mu_x = 4, all 25 (mu_y, mu_z)) also reads the tables;
+    // k-steps 0-4 give lane group g mu_y = g with mu_z = step, k-step 5 gives
+    // mu_y = 4 with mu_z = g, and k-step 6 the last pair (4, 4) to group 0
+    constexpr bool kTail5 = kTables && M == 5;
 
     // B operands of a block: x rows through L2
     auto load_b = [&](int b, T* bv) {
@@ -524,12 +528,21 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int p = 0; p < MM; ++p) bv[q * MM + p] = X[(4 * q + g + M * p) * RHS_TILE];
+        if constexpr (kTail5) {
 #pragma unroll
-        for (int ts = 0; ts < KS_TAIL; ++ts) {
-            const int c = 4 * ts + g;
-            const int cc = c < R * MM ? c : 0;
-            const T v = X[(4 * Q + cc % R + M * (cc / R)) * RHS_TILE];
-            bv[Q * MM + ts] = c < R * MM ? v : T(0);
+            for (int ts = 0; ts < KS_TAIL; ++ts) {
+                const int mu = ts < 5 ? 4 + M * (g + M * ts) : (ts == 5 ? 4 + M * (4 + M * g) : K - 1);
+                const T v = X[mu * RHS_TILE];
+                bv[Q * MM + ts] = ts < 6 || g == 0 ? v : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int ts = 0; ts < KS_TAIL; ++ts) {
+                const int c = 4 * ts + g;
+                const int cc = c < R * MM ? c : 0;
+                const T v = X[(4 * Q + cc % (R > 0 ? R : 1) + M * (cc / (R > 0 ? R : 1))) * RHS_TILE];
+                bv[Q * MM + ts] = c < R * MM ? v : T(0);
+            }
         }
     };
     auto block = [&](int b, const T* bv) {
@@ -543,6 +556,18 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
             ay[r] = dy0 + sot[1][16 * (r0 + r) + i];
             az[r] = dz0 + sot[2][16 * (r0 + r) + i];
         }
+        // dy^2 and dz^2 per row and node, for the tables of every k-step
+        T dy2[kTables ? RT : 1][kTables ? M : 1], dz2[kTables ? RT : 1][kTables ? M : 1];
+        if constexpr (kTables) {
+#pragma unroll
+            for (int r = 0; r < RT; ++r)
+#pragma unroll
+                for (int l = 0; l < M; ++l) {
+                    const T ey = ay[r] - hsy * u[l], ez = az[r] - hsz * u[l];
+                    dy2[r][l] = ey * ey;
+                    dz2[r][l] = ez * ez;
+                }
+        }
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const T osx = hsx * su[4 * q + g];
@@ -553,16 +578,12 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
                 dx2[r] = e * e;
             }
             // |d|^2 = (dx^2 + dy^2)[row][mu_y] + dz^2[row][mu_z]
-            T dxy2[kTables ? RT : 1][kTables ? M : 1], dz2[kTables ? RT : 1][kTables ? M : 1];
+            T dxy2[kTables ? RT : 1][kTables ? M : 1];
             if constexpr (kTables) {
 #pragma unroll
                 for (int r = 0; r < RT; ++r)
 #pragma unroll
-                    for (int l = 0; l < M; ++l) {
-                        const T ey = ay[r] - hsy * u[l], ez = az[r] - hsz * u[l];
-                        dxy2[r][l] = dx2[r] + ey * ey;
-                        dz2[r][l] = ez * ez;
-                    }
+                    for (int l = 0; l < M; ++l) dxy2[r][l] = dx2[r] + dy2[r][l];
             }
 #pragma unroll
             for (int p = 0; p < MM; ++p) {
@@ -579,18 +600,40 @@ __device__ inline void coupling_gen_item(const ProductArgs& a, const UnitNodes& 
                 }
             }
         }
-#pragma unroll
-        for (int ts = 0; ts < KS_TAIL; ++ts) {
-            const int c = 4 * ts + g;
-            const bool ok = c < R * MM;
-            const int cc = ok ? c : 0;
-            const int p = cc / R;
-            const T osx = hsx * su[4 * Q + cc % R], osy = hsy * su[p % M], osz = hsz * su[p / M];
+        if constexpr (kTail5) {
+            const T ug = su[g], osx = hsx * su[4];
+            T base[RT], b4[RT], ezg2[RT];
 #pragma unroll
             for (int r = 0; r < RT; ++r) {
-                const T ex = ax[r] - osx, ey = ay[r] - osy, ez = az[r] - osz;
-                const T d2 = ex * ex + ey * ey + ez * ez;
-                acc[r] = Mfma<T>::mma(rsqrt_kernel<T>(d2), bv[Q * MM + ts], acc[r]);
+                const T ex = ax[r] - osx, eyg = ay[r] - hsy * ug, ezg = az[r] - hsz * ug;
+                const T dx2 = ex * ex;
+                base[r] = dx2 + eyg * eyg;             // mu_x = 4, mu_y = g
+                b4[r] = dx2 + dy2[r][4];               // mu_x = 4, mu_y = 4
+                ezg2[r] = ezg * ezg;                   // mu_z = g
+            }
+#pragma unroll
+            for (int ts = 0; ts < 5; ++ts)
+#pragma unroll
+                for (int r = 0; r < RT; ++r)
+                    acc[r] = Mfma<T>::mma(rsqrt_kernel<T>(base[r] + dz2[r][ts]), bv[Q * MM + ts], acc[r]);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = Mfma<T>::mma(rsqrt_kernel<T>(b4[r] + ezg2[r]), bv[Q * MM + 5], acc[r]);
+#pragma unroll
+            for (int r = 0; r < RT; ++r) acc[r] = Mfma<T>::mma(rsqrt_kernel<T>(b4[r] + dz2[r][4]), bv[Q * MM + 6], acc[r]);
+        } else {
+#pragma unroll
+            for (int ts = 0; ts < KS_TAIL; ++ts) {
+                const int c = 4 * ts + g;
+                const bool ok = c < R * MM;
+                const int cc = ok ? c : 0;
+                const int p = cc / (R > 0 ? R : 1);
+                const T osx = hsx * su[4 * Q + cc % (R > 0 ? R : 1)], osy = hsy * su[p % M], osz = hsz * su[p / M];
+#pragma unroll
+                for (int r = 0; r < RT; ++r) {
+                    const T ex = ax[r] - osx, ey = ay[r] - osy, ez = az[r] - osz;
+                    const T d2 = ex * ex + ey * ey + ez * ez;
+                    acc[r] = Mfma<T>::mma(rsqrt_kernel<T>(d2), bv[Q * MM + ts], acc[r]);
+                }
             }
         }
     };
@@ -976,14 +1019,12 @@ inline int pow2ceil(int v) {
 }
 
 template <typename T, int EPI>
-hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nrg, hipStream_t st,
-                    size_t lds_floor = 0) {
+hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nrg, hipStream_t st) {
     const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
     if (grid == 0) return hipSuccess;
     const int nbg = kWaves / nrg;
     size_t lds = size_t(nbg - 1) * nrg * rtw * 256 * sizeof(T);
     if (EPI == EPI_LEAF) lds += size_t(16 * rtw) * RHS_TILE * sizeof(T);   // staged output rows
-    lds = std::max(lds, lds_floor);
 #define H2DLP_CASE(RTW_, NRG_)                                                                       \
     if (rtw == RTW_ && nrg == NRG_) {                                                                \
         hipLaunchKernelGGL((k_product<T, RTW_, NRG_, EPI>), dim3(grid), dim3(kThreads), lds, st, a, e); \
@@ -1073,7 +1114,7 @@ hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows
     return dispatch<float, EPI_STORE>(a, none, rtw, nrg, st);
 }
 
-hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipStream_t st) {
+hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, size_t lds_floor, hipStream_t st) {
     if (m < 1 || m > 5 || (prec != P_FP32 && prec != P_FP64)) return hipErrorInvalidValue;
     const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
     if (grid == 0) return hipSuccess;
@@ -1081,7 +1122,8 @@ hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipS
     for (int l = 0; l < m; ++l) un.o[l] = std::cos((2.0 * l + 1.0) * 3.14159265358979323846 / (2.0 * m));
     const int rt = (m * m * m + 15) / 16;
     // orders 4 and 5 split rows over waves (no LDS reduction); lower orders split blocks
-    const size_t lds = m >= 4 ? 0 : size_t(kWaves - 1) * rt * 256 * (prec == P_FP64 ? 8 : 4);
+    const size_t lds = std::max(m >= 4 ? size_t(0) : size_t(kWaves - 1) * rt * 256 * (prec == P_FP64 ? 8 : 4),
+                                lds_floor);
 #define H2DLP_GEN_LAUNCH(MM, ROWS)                                                                              \
     if (prec == P_FP64)                                                                                         \
         hipLaunchKernelGGL((k_coupling_gen<double, MM, ROWS>), dim3(grid), dim3(kThreads), lds, st, a, un);    \
@@ -1154,12 +1196,11 @@ hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hip
     return dispatch<float, EPI_ADD64>(a, e, rtw, nrg, st);
 }
 
-hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, size_t lds_floor,
-                               hipStream_t st) {
+hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st) {
     const int rtw = pow2ceil(a.rt);
     if (rtw > 8) return hipErrorInvalidValue;
-    if (prec == P_FP64) return dispatch<double, EPI_LEAF>(a, e, rtw, 1, st, lds_floor);
-    return dispatch<float, EPI_LEAF>(a, e, rtw, 1, st, lds_floor);
+    if (prec == P_FP64) return dispatch<double, EPI_LEAF>(a, e, rtw, 1, st);
+    return dispatch<float, EPI_LEAF>(a, e, rtw, 1, st);
 }
 
 hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, const int32_t* child1, const void* e,

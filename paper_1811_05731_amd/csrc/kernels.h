@@ -84,10 +84,7 @@ hipError_t launch_unpermute(const double* y64, int io, int64_t n_nodes, int nr, 
                             hipStream_t st);
 // prefer_rows: split the rows of one item over the 4 waves (else split its blocks)
 hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st);
-// lds_floor: LDS bytes each workgroup reserves at least (occupancy shaping
-// when the near field shares the device with the coupling products)
-hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, size_t lds_floor,
-                               hipStream_t st);
+hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st);
 // Coupling products; for k <= 128 with ceil(k/16) a power of two the blocks are
 // stored k x coupling_cols(k) (zero columns beyond k) and a pipelined kernel runs.
 hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st);
@@ -95,7 +92,9 @@ hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st
 hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hipStream_t st);
 // Generated coupling (orders 1..5, FP32 or FP64): a.pool holds the per-cluster
 // centre and half extent (6 doubles, level-order ids), blks[b].a_off the source cluster.
-hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, hipStream_t st);
+// lds_floor: LDS bytes each workgroup reserves at least (occupancy shaping
+// while the near field shares the device).
+hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, size_t lds_floor, hipStream_t st);
 inline int coupling_cols(int k) {
     const int rt = (k + 15) / 16;
     return (rt <= 8 && (rt & (rt - 1)) == 0) ? 16 * rt : k;
