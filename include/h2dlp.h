@@ -195,7 +195,7 @@ const char* h2dlp_last_error(void);
  * the stream each launch goes to.  Kinds: 0 permute, 1 leaf forward, 2 upward
  * transfer, 3 coupling, 4 downward transfer, 5 leaf backward V_t yhat_t (+
  * un-permute), 6 near field + diagonal.  The near field runs on a stream of
- * the handle's own, concurrently with kinds 1-4, so kind times overlap.  `enable` is a bit mask: bit q records kind q
+ * the handle's own, concurrently with kinds 3 and 4, so kind times overlap.  `enable` is a bit mask: bit q records kind q
  * (0 = off, H2DLP_PROFILE_ALL = every kind); record only the kinds you need,
  * since every event pair adds a little time to the stream.
  * h2dlp_profile_read synchronises the recorded events and returns the summed
