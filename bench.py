@@ -6,9 +6,11 @@ to 16 right-hand sides on the level-8 icosphere (655362 boundary nodes), order
 5, leaf 64, eta 2.  Inputs are resident in HBM before the timed region.
 
 Prints one JSON line.  `value` is boundary degrees of freedom per second
-(N * nrhs / t_apply / 1e9).  `roofline` is computed for the dominant kernel
-(the coupling products) from its HIP-event time inside the timed region.
-`cpu_baseline` times the CPU oracle on a bounded sample of the same workload.
+(N * nrhs / t_apply / 1e9).  `rooflines` holds a record for the coupling
+products and one for the near field, each from its HIP-event time inside the
+timed region; `roofline` is the dominant one, whose algorithmic work at its
+own peak takes longer.  `cpu_baseline` times the CPU oracle on a bounded
+sample of the same workload.
 """
 from __future__ import annotations
 
@@ -26,7 +28,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H² DLP matvec boundary GDOF/s + %HBM roofline; serve p50/p99 at 1e-6 rel err"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("paper_1811_05731_amd/csrc/apply_kernels.hip", "paper_1811_05731_amd/csrc/layout.h")
+KERNEL_SOURCES = ("paper_1811_05731_amd/csrc/apply_kernels.hip", "paper_1811_05731_amd/csrc/layout.h",
+                  "paper_1811_05731_amd/csrc/kernels.h", "paper_1811_05731_amd/csrc/api.cpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sphere_l8.json")
 RHS_PER_PASS = 16
 DEFAULT_COUPLING = "generated"

@@ -1,0 +1,53 @@
+"""Host-side logic of bench.py: exact-block thresholds, the roofline
+arithmetic of the reported records, and the one-GPU contract."""
+import os
+import subprocess
+import sys
+import types
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_default_thresholds():
+    assert bench.default_dense_far_max(5, "stored") == 125 ** 2
+    assert bench.default_dense_far_max(5, "generated") == 125 ** 2 // 2
+    assert bench.default_dense_far_max(4, "generated") == 64 ** 2 // 2
+
+
+def test_coupling_records():
+    st = types.SimpleNamespace(coupling_entries=10 * 125 ** 2, n_clusters=7, k=125)
+    # generated: 2 flops per entry and right-hand side, 16 right-hand sides per pass
+    flops = 2.0 * 10 * 125 ** 2 * 16
+    assert bench.coupling_flops(st) == flops
+    r = bench.roofline_of(st, "fp32", "generated", {"coupling": (4.0, 2)}, 1000)    # 2 ms per launch
+    assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
+    assert abs(r["achieved"] - flops / 2e-3 / 1e12) < 0.01
+    assert abs(r["roofline_ms"] - flops / 157.3e12 * 1e3) < 1e-4
+    # stored: every entry once, xhat read and yhat written once per cluster
+    b = 10 * 125 ** 2 * 4 + 2 * 7 * 125 * 16 * 4
+    assert bench.coupling_alg_bytes(st, 4, 4) == b
+    r = bench.roofline_of(st, "fp32", "stored", {"coupling": (1.0, 1)}, 1000)
+    assert r["bound"] == "hbm" and r["alg_bytes_per_launch"] == b
+    assert abs(r["frac"] - b / 1e-3 / 1e9 / 8000.0) < 1e-4
+    # FP64 and BF16X6 entries are 8 and 6 bytes
+    assert bench.roofline_of(st, "fp64", "stored", {"coupling": (1.0, 1)}, 1000)["alg_bytes_per_launch"] == \
+        10 * 125 ** 2 * 8 + 2 * 7 * 125 * 16 * 8
+    assert bench.roofline_of(st, "bf16x6", "stored", {"coupling": (1.0, 1)}, 1000)["alg_bytes_per_launch"] == \
+        10 * 125 ** 2 * 6 + 2 * 7 * 125 * 16 * 4
+
+
+def test_near_field_record():
+    st = types.SimpleNamespace(bytes_near=10 ** 6)
+    # FP32: x (4 B), x64 (8 B) read and y64 (8 B) written per node and column
+    assert bench.near_field_alg_bytes(st, 4, 100) == 10 ** 6 + 100 * 16 * 20
+    assert bench.near_field_alg_bytes(st, 8, 100) == 10 ** 6 + 100 * 16 * 16
+    r = bench.near_field_roofline(st, "fp32", {"near_field": (3.0, 3)}, 100)
+    assert r["bound"] == "hbm" and abs(r["achieved"] - (10 ** 6 + 32000) / 1e-3 / 1e9) < 0.1
+
+
+def test_more_than_one_gpu_is_refused():
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
