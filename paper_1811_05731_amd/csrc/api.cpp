@@ -387,6 +387,11 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         h->items_near.push_back(ItemDesc{d.out_row, d.m, d.blk_begin + 1, d.blk_end});
         h->items_v.push_back(ItemDesc{d.out_row, d.m, d.blk_begin, d.blk_begin + 1});
     }
+    // near-field items in node (depth-first) order rather than level order:
+    // neighbouring items, dealt to one XCD in chunks, are then neighbouring
+    // leaves whatever their level, and share source rows of x in that L2
+    std::stable_sort(h->items_near.begin(), h->items_near.end(),
+                     [](const ItemDesc& a, const ItemDesc& b) { return a.out_row < b.out_row; });
     h->rt_leaf = (o->leaf + 15) / 16;
     h->off_wt = off_wt;
     h->off_s = off_s;
