@@ -39,6 +39,8 @@ the library by specification only, never by code):
 """
 from __future__ import annotations
 
+import copy
+
 import numpy as np
 
 from . import geometry, lindholm, quadrature
@@ -213,12 +215,7 @@ class H2Oracle:
         (self.perm, self.begin, self.end, self.level, self.parent,
          self.child0, self.child1) = build_cluster_tree(self.xyz, leaf)
         self.lo, self.hi = support_boxes(self.xyz, self.tri, self.perm, self.begin, self.end, alpha)
-        far_all, self.near = build_block_tree(self.lo, self.hi, self.child0, self.child1, eta)
-        # an admissible block with |t| |s| <= dense_far_max keeps its exact
-        # entries (Section 3) instead of the interpolation factors
-        size = self.end - self.begin
-        small = size[far_all[:, 0]] * size[far_all[:, 1]] <= dense_far_max
-        self.far, self.far_dense = far_all[~small], far_all[small]
+        self.far_all, self.near = build_block_tree(self.lo, self.hi, self.child0, self.child1, eta)
         self.pts = chebyshev_points(self.lo, self.hi, order)
         self.normals, self.areas = geometry.triangle_normals_areas(self.xyz, self.tri)
         self.inc_off, self.inc_tri, self.inc_loc = geometry.incidence(self.xyz.shape[0], self.tri)
@@ -228,12 +225,29 @@ class H2Oracle:
         self.cache_coupling = cache_coupling
         self._W, self._V, self._E, self._K, self._S = {}, {}, {}, {}, {}
         C = self.begin.size
-        self.far_of = [[] for _ in range(C)]
-        for t, s in self.far:
-            self.far_of[t].append(int(s))
+        self._split_far(dense_far_max)
         self.near_of = [[] for _ in range(C)]
         for t, s in self.near:
             self.near_of[t].append(int(s))
+
+    def _split_far(self, dense_far_max):
+        """Admissible blocks with |t| |s| <= dense_far_max keep their exact
+        entries (Section 3) instead of the interpolation factors."""
+        size = self.end - self.begin
+        small = size[self.far_all[:, 0]] * size[self.far_all[:, 1]] <= dense_far_max
+        self.far, self.far_dense = self.far_all[~small], self.far_all[small]
+        self.dense_far_max = dense_far_max
+        self.far_of = [[] for _ in range(self.begin.size)]
+        for t, s in self.far:
+            self.far_of[t].append(int(s))
+
+    def with_dense_far_max(self, dense_far_max):
+        """The same matrix with another exact-block threshold.  The tree, the
+        boxes and every cached basis, transfer and exact block are shared: none
+        of them depends on which admissible blocks are kept exact."""
+        other = copy.copy(self)
+        other._split_far(dense_far_max)
+        return other
 
     # -- structure -----------------------------------------------------------
     @property
@@ -396,6 +410,64 @@ class H2Oracle:
         y += self.D[:, None] * x
         out = y.T
         return out[0] if squeeze else out
+
+    def apply_rows(self, u1: np.ndarray, rows, xh=None) -> np.ndarray:
+        """Rows `rows` (node indices) of u2 = (K_H2 + D) u1: shape (r, len(rows)).
+
+        The same steps as apply(): the full upward pass (or `xh`, a forward()
+        result for the same u1), then the coupling and the downward pass only
+        for the clusters on the root paths of the leaves holding the rows, the
+        rows of V_t there, and the exact blocks of those clusters.
+        """
+        u = np.atleast_2d(np.asarray(u1, dtype=np.float64))
+        x = u.T.copy()
+        rows = np.asarray(rows, dtype=np.int64)
+        if xh is None:
+            xh = self.forward(x)
+        N = self.xyz.shape[0]
+        pos = np.empty(N, dtype=np.int64)
+        pos[self.perm] = np.arange(N)
+        # every cluster whose index range holds a requested row (root paths)
+        on_path = np.zeros(self.n_clusters, dtype=bool)
+        for p in np.unique(pos[rows]):
+            c = 0
+            while True:
+                on_path[c] = True
+                if self.is_leaf(c):
+                    break
+                c = self.child0[c] if p < self.end[self.child0[c]] else self.child1[c]
+        # coupling and downward pass along the paths (parents precede children)
+        yt = [None] * self.n_clusters
+        for t in np.where(on_path)[0]:
+            acc = None
+            for s in self.far_of[t]:
+                if xh[s] is not None:
+                    v = self.S(t, s) @ xh[s]
+                    acc = v if acc is None else acc + v
+            p = self.parent[t]
+            if p >= 0 and yt[p] is not None:
+                v = self.E(t) @ yt[p]
+                acc = v if acc is None else acc + v
+            yt[t] = acc
+        exact_of = {}
+        for t, s in np.concatenate([self.near, self.far_dense]):
+            if on_path[t]:
+                exact_of.setdefault(int(t), []).append(int(s))
+        out = np.empty((x.shape[1], rows.size))
+        for q, i in enumerate(rows):
+            acc = self.D[i] * x[i]
+            c = 0
+            while True:
+                li = pos[i] - self.begin[c]                 # local row of i in cluster c
+                for s in exact_of.get(c, ()):
+                    acc = acc + self.K_near(c, s)[li] @ x[self.nodes(s)]
+                if self.is_leaf(c):
+                    if yt[c] is not None:
+                        acc = acc + self.V(c)[li] @ yt[c]
+                    break
+                c = self.child0[c] if pos[i] < self.end[self.child0[c]] else self.child1[c]
+            out[:, q] = acc
+        return out
 
     # -- sizes -------------------------------------------------------------------
     def counts(self) -> dict:

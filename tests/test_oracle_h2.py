@@ -215,3 +215,40 @@ def test_dense_far_blocks():
     e0 = np.linalg.norm(plain.apply(u) - ref, axis=1) / np.linalg.norm(ref, axis=1)
     e1 = np.linalg.norm(part.apply(u) - ref, axis=1) / np.linalg.norm(ref, axis=1)
     assert np.all(e1 < e0), (e0, e1)
+
+
+def test_dense_far_max_view_equals_fresh_build():
+    # re-splitting an existing oracle gives the operator a fresh build with the
+    # same threshold gives (shared pieces do not depend on the split)
+    xyz, tri = meshes.icosphere(3, 0.01, 3)
+    u = rhs.normal_rhs(xyz.shape[0], 2, 4)
+    plain = h2.H2Oracle(xyz, tri, order=3, leaf=16, eta=2.0)
+    plain.apply(u)                                           # fill the caches first
+    for d in (27 * 27, 16 * 16):
+        view = plain.with_dense_far_max(d)
+        fresh = h2.H2Oracle(xyz, tri, order=3, leaf=16, eta=2.0, dense_far_max=d)
+        assert np.array_equal(view.far, fresh.far) and np.array_equal(view.far_dense, fresh.far_dense)
+        assert np.array_equal(view.apply(u), fresh.apply(u))
+    assert plain.far_dense.shape[0] == 0                    # the original keeps its own split
+
+
+def test_rows_of_the_product():
+    # the row-restricted product against the whole product, and with every
+    # block exact against rows of the dense matrix (Section 3)
+    xyz, tri = meshes.icosphere(3, 0.02, 6)
+    N = xyz.shape[0]
+    M = dense.dense_m(xyz, tri)
+    u = np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(N, 2, 12)])
+    rows = np.random.default_rng(5).choice(N, 37, replace=False)
+    H = h2.H2Oracle(xyz, tri, order=3, leaf=12, eta=2.0)
+    for d in (0, 12 * 12, N * N):
+        Hd = H.with_dense_far_max(d)
+        full = Hd.apply(u)
+        got = Hd.apply_rows(u, rows)
+        np.testing.assert_allclose(got, full[:, rows], rtol=0, atol=1e-14 * np.abs(full).max())
+    exact = (u @ M.T)[:, rows]
+    np.testing.assert_allclose(H.with_dense_far_max(N * N).apply_rows(u, rows), exact, rtol=0,
+                               atol=1e-13 * np.abs(exact).max())
+    # a precomputed upward pass gives the same rows
+    x = u.T.copy()
+    np.testing.assert_array_equal(H.apply_rows(u, rows, xh=H.forward(x)), H.apply_rows(u, rows))
