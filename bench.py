@@ -180,101 +180,201 @@ def sphere_check(op, xyz, dev) -> dict:
             "u1_one_max_err": float(f"{np.max(np.abs(u2[1] + 1.0)):.3e}")}
 
 
-def cpu_baseline(xyz, tri, case, nrhs: int, frac: float = 0.01, seed: int = 7) -> dict:
-    """The oracle's apply timed on a bounded sample of the same workload.
+def host_cpu() -> dict:
+    """The host's CPU model and the cores the CPU baseline uses: the CPUs this
+    process may run on, at most 16 (one GPU's share of its host)."""
+    visible = len(os.sched_getaffinity(0))
+    model = None
+    with open("/proc/cpuinfo") as f:
+        for line in f:
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    return {"cores": min(16, visible), "visible_cpus": visible, "model": model}
 
-    The oracle's matvec is a loop over work items (leaves, clusters, far
-    blocks, near blocks).  A seeded sample `frac` of each kind of item is
-    timed through the oracle's own routines, with the coupling matrices
-    generated on the fly as the oracle does at this size; the full-apply time
-    is the per-item time times the item counts.  Pieces the oracle builds once
-    (bases, transfers, near blocks) are built outside the timed region.
+
+_CPU = {}        # state the forked CPU-baseline workers inherit
+
+
+def _sample_worker(q: int):
+    """Worker q of the sampled oracle apply: build its items' pieces (untimed),
+    wait for every worker, then time its share of the sampled items."""
+    from threadpoolctl import threadpool_limits
+    H, x, xh, items = _CPU["H"], _CPU["x"], _CPU["xh"], _CPU["items"][q]
+    with threadpool_limits(limits=1):
+        for kind, a in items:                       # pieces the oracle builds once per operator
+            if kind == "leaf":
+                H.W(a), H.V(a)
+            elif kind == "up":
+                H.E(H.child0[a]), H.E(H.child1[a])
+            elif kind == "down":
+                H.E(a)
+            elif kind in ("near", "dense"):
+                H.K_near(*a)
+        _CPU["barrier"].wait()
+        t0 = time.perf_counter()
+        for kind, a in items:
+            if kind == "leaf":
+                _ = H.W(a).T @ x[H.nodes(a)]
+                _ = H.V(a) @ xh
+            elif kind == "up":
+                _ = H.E(H.child0[a]).T @ xh + H.E(H.child1[a]).T @ xh
+            elif kind == "down":
+                _ = H.E(a) @ xh
+            elif kind == "far":
+                _ = H.S(*a) @ xh                    # generated on the fly, as the oracle does here
+            else:
+                _ = H.K_near(*a) @ x[H.nodes(a[1])]
+        t1 = time.perf_counter()
+    return t0, t1
+
+
+def _fill_worker(args):
+    """Pieces of the oracle built in a worker for the parent's caches."""
+    kind, chunk = args
+    H = _CPU["H"]
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        if kind == "W":
+            return kind, [(int(c), H.W(c)) for c in chunk]
+        if kind == "K":
+            return kind, [((int(t), int(s)), H.K_near(t, s)) for t, s in chunk]
+        return kind, [((int(t), int(s)), H.S(t, s)) for t, s in chunk]
+
+
+def oracle_sample(xyz, tri, case, nrhs: int, dense_far_max: int, cores: int, frac: float = 0.05,
+                  seed: int = 7) -> dict:
+    """The oracle's apply of the benchmarked operator, timed on a sample.
+
+    The oracle's matvec is a loop over work items: leaves (W_s^T x, V_t yhat),
+    upward and downward transfers, low-rank far blocks (S_ts generated on the
+    fly, as the GPU path does), near blocks and exact admissible blocks.  A
+    seeded fraction `frac` of every kind is dealt over `cores` worker
+    processes (one BLAS thread each).  Each worker first builds the pieces the
+    oracle builds once per operator (bases, transfers, exact blocks; untimed),
+    then all time their items together; the whole-apply estimate is that wall
+    time divided by `frac`.
     """
+    from multiprocessing import get_context
+
+    from oracle import h2
+    t0 = time.perf_counter()
+    H = h2.H2Oracle(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, cache_coupling=False,
+                    dense_far_max=dense_far_max)
+    t_struct = time.perf_counter() - t0
+    rng = np.random.default_rng(seed)
+    C = H.n_clusters
+    kinds = {"leaf": list(np.where(H.child0 < 0)[0]), "up": list(np.where(H.child0 >= 0)[0]),
+             "down": list(range(1, C)), "far": [tuple(b) for b in H.far], "near": [tuple(b) for b in H.near],
+             "dense": [tuple(b) for b in H.far_dense]}
+    items, counts = [], {}
+    for kind, lst in kinds.items():
+        if not lst:
+            continue
+        pick = rng.choice(len(lst), max(1, int(round(frac * len(lst)))), replace=False)
+        items += [(kind, lst[p]) for p in pick]
+        counts[kind] = (len(pick), len(lst))
+    order = rng.permutation(len(items))
+    ctx = get_context("fork")
+    _CPU.update(H=H, x=rng.normal(size=(xyz.shape[0], nrhs)), xh=rng.normal(size=(H.k, nrhs)),
+                items=[[items[o] for o in order[q::cores]] for q in range(cores)], barrier=ctx.Barrier(cores))
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        spans = pool.map(_sample_worker, range(cores))
+    t_run = time.perf_counter() - t0
+    wall = max(b for _, b in spans) - min(a for a, _ in spans)
+    t0 = time.perf_counter()
+    _ = H.D[:, None] * _CPU["x"]
+    t_diag = time.perf_counter() - t0
+    _CPU.clear()
+    est = wall / frac + t_diag
+    n = xyz.shape[0]
+    return {"value": n * nrhs / est / 1e9, "unit": "GDOF/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{frac:.0%} of every item kind of the benchmarked operator (seed {seed}): "
+                       + ", ".join(f"{k} {a}/{b}" for k, (a, b) in counts.items())
+                       + f"; dealt over {cores} processes with one BLAS thread each; whole-apply time = "
+                         f"their common wall time / {frac:g}; S_ts generated on the fly"),
+            "est_apply_s": round(est, 3), "sample_wall_s": round(wall, 4),
+            "oracle_structure_s": round(t_struct, 2), "piece_build_and_sample_s": round(t_run, 2)}
+
+
+def oracle_direct(case_name: str, cores: int, dense_far_max: int = 0, reps: int = 3) -> dict:
+    """The oracle's whole apply timed directly (median of `reps`) on a named
+    workload, after one apply that builds its pieces.  Bases, exact blocks and
+    coupling matrices of that first apply are computed by `cores` worker
+    processes into the oracle's own caches (logged as the oracle's build)."""
+    from multiprocessing import get_context
+
+    from threadpoolctl import threadpool_limits
+
+    from oracle import h2
+    case, xyz, tri = workload(case_name)
+    u1, _ = case_rhs(case, xyz)
+    t0 = time.perf_counter()
+    H = h2.H2Oracle(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, dense_far_max=dense_far_max)
+    _CPU["H"] = H
+    jobs = [("W", c) for c in np.array_split(np.where(H.child0 < 0)[0], 4 * cores)]
+    jobs += [("K", c) for c in np.array_split(np.concatenate([H.near, H.far_dense]), 8 * cores)]
+    jobs += [("S", c) for c in np.array_split(H.far, 8 * cores)]
+    with get_context("fork").Pool(cores) as pool:
+        for kind, part in pool.imap_unordered(_fill_worker, jobs):
+            cache = {"W": H._W, "K": H._K, "S": H._S}[kind]
+            for key, val in part:
+                cache[key] = val
+    _CPU.clear()
+    with threadpool_limits(limits=cores):
+        H.apply(u1)                                            # transfers and V; everything else cached
+        t_build = time.perf_counter() - t0
+        times = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            H.apply(u1)
+            times.append(time.perf_counter() - t0)
+    t = float(np.median(times))
+    n = xyz.shape[0]
+    return {"workload": case_name, "nodes": n, "rhs": u1.shape[0], "dense_far_max": dense_far_max,
+            "apply_s_median": round(t, 4), "apply_s": [round(v, 4) for v in times],
+            "GDOF_s": n * u1.shape[0] / t / 1e9, "build_s": round(t_build, 1),
+            "note": f"coupling matrices cached after the first apply; BLAS at {cores} threads"}
+
+
+def cpu_baseline(xyz, tri, case, nrhs: int, dense_far_max: int, direct_c2: bool = True) -> dict:
+    """The CPU oracle beside the GPU: the benchmarked operator on a sample
+    (`value`), the 2562-node sphere timed directly (dense matvec and whole H2
+    apply, median of 3) and, unless disabled, the 163842-node sphere's whole
+    apply timed directly."""
     from threadpoolctl import threadpool_limits
 
     from oracle import dense, h2
     from workloads import cases, rhs
-
-    # the 2562-node sphere: dense matvec and the oracle's whole H2 apply, timed directly
+    host = host_cpu()
+    cores = host["cores"]
+    out = oracle_sample(xyz, tri, case, nrhs, dense_far_max, cores)
+    out["cpu_model"] = host["model"]
+    out["visible_cpus"] = host["visible_cpus"]
     c1 = cases.CASES["sphere_l4"]
     x1, t1 = cases.mesh_of(c1.mesh)
     M = dense.dense_m(x1, t1)
     u = np.vstack([rhs.z_rhs(x1), rhs.normal_rhs(x1.shape[0], 1, 0)])
     H1 = h2.H2Oracle(x1, t1, order=c1.order, leaf=c1.leaf, eta=c1.eta)
     H1.apply(u)                                            # builds the pieces once
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
+    with threadpool_limits(limits=cores):
+        td, th = [], []
         for _ in range(3):
+            t0 = time.perf_counter()
             _ = u @ M.T
-        t_dense = (time.perf_counter() - t0) / 3
-        t0 = time.perf_counter()
-        H1.apply(u)
-        t_h2 = time.perf_counter() - t0
+            td.append(time.perf_counter() - t0)
+            t0 = time.perf_counter()
+            H1.apply(u)
+            th.append(time.perf_counter() - t0)
     del M, H1
-
-    t_build0 = time.perf_counter()
-    H = h2.H2Oracle(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, cache_coupling=False)
-    t_struct = time.perf_counter() - t_build0
-    rng = np.random.default_rng(seed)
-    C = H.n_clusters
-    leaves = np.where(H.child0 < 0)[0]
-    inner = np.where(H.child0 >= 0)[0]
-    nonroot = np.arange(1, C)
-    pick = lambda a: rng.choice(a, max(1, int(round(frac * len(a)))), replace=False)  # noqa: E731
-    s_leaf, s_inner, s_far, s_near, s_down = pick(leaves), pick(inner), pick(np.arange(len(H.far))), \
-        pick(np.arange(len(H.near))), pick(nonroot)
-    k = H.k
-    x = rng.normal(size=(xyz.shape[0], nrhs))
-    xh = rng.normal(size=(k, nrhs))
-    # build-time pieces of the sampled items (untimed)
-    for c in s_leaf:
-        H.W(c), H.V(c)
-    for c in s_inner:
-        H.E(H.child0[c]), H.E(H.child1[c])
-    for c in s_down:
-        H.E(c)
-    for b in s_near:
-        H.K_near(*H.near[b])
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for c in s_leaf:
-            _ = H.W(c).T @ x[H.nodes(c)]
-            _ = H.V(c) @ xh
-        t_leaf = (time.perf_counter() - t0) / len(s_leaf)
-        t0 = time.perf_counter()
-        for c in s_inner:
-            _ = H.E(H.child0[c]).T @ xh + H.E(H.child1[c]).T @ xh
-        t_up = (time.perf_counter() - t0) / len(s_inner)
-        t0 = time.perf_counter()
-        for c in s_down:
-            _ = H.E(c) @ xh
-        t_down = (time.perf_counter() - t0) / len(s_down)
-        t0 = time.perf_counter()
-        for b in s_far:
-            t, s = H.far[b]
-            _ = H.S(t, s) @ xh
-        t_far = (time.perf_counter() - t0) / len(s_far)
-        t0 = time.perf_counter()
-        for b in s_near:
-            t, s = H.near[b]
-            _ = H.K_near(t, s) @ x[H.nodes(s)]
-        t_near = (time.perf_counter() - t0) / len(s_near)
-        t0 = time.perf_counter()
-        _ = H.D[:, None] * x
-        t_diag = time.perf_counter() - t0
-    total = (t_leaf * len(leaves) + t_up * len(inner) + t_down * len(nonroot) + t_far * len(H.far)
-             + t_near * len(H.near) + t_diag)
-    n = xyz.shape[0]
-    return {
-        "value": n * nrhs / total / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-        "sample": (f"{frac:.0%} of each item kind of the same operator, seed {seed}: {len(s_leaf)} leaves, "
-                   f"{len(s_inner)} upward and {len(s_down)} downward transfers, {len(s_far)} far blocks "
-                   f"(coupling generated on the fly), {len(s_near)} near blocks; full-apply time = per-item "
-                   f"time x item counts; NumPy FP64, BLAS limited to one thread"),
-        "est_apply_s": total, "oracle_structure_s": round(t_struct, 2),
-        "sphere_l4": {"nodes": int(x1.shape[0]), "rhs": 2, "dense_matvec_s": t_dense, "h2_apply_s": round(t_h2, 4),
-                      "h2_GDOF_s": x1.shape[0] * 2 / t_h2 / 1e9},
-    }
+    out["direct"] = {"sphere_l4": {"nodes": int(x1.shape[0]), "rhs": 2, "dense_matvec_s_median": float(np.median(td)),
+                                   "h2_apply_s_median": round(float(np.median(th)), 4),
+                                   "h2_GDOF_s": x1.shape[0] * 2 / float(np.median(th)) / 1e9}}
+    if direct_c2:
+        c2 = cases.CASES["sphere_l7"]
+        out["direct"]["sphere_l7"] = oracle_direct("sphere_l7", cores, default_dense_far_max(c2.order, DEFAULT_COUPLING))
+    return out
 
 
 def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4, coupling: str = "stored",
@@ -319,7 +419,8 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4,
             "slots_GB": round(srv.fixed_bytes() / 1e9, 2),
             "slots": n_slots, "precision": "fp32", "coupling": coupling, "dense_far_max": "k^2" if dense_far else 0,
             "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
-            "reloads": sum(st["reloads"].values()), "offloads": sum(st["offloads"].values())}
+            "reloads": sum(st["reloads"].values()), "offloads": sum(st["offloads"].values()),
+            "breakdown_ms": st["breakdown_ms"]}
 
 
 MFMA_PEAK_TFS = {"fp32": 157.3, "fp64": 78.6}     # dense MFMA peaks of MI355X
@@ -368,6 +469,63 @@ def roofline_of(st, prec: str, coupling: str, kernels: dict, n_nodes: int) -> di
             "roofline_ms": round(b / HBM_PEAK_GBS / 1e6, 4)}
 
 
+def apply_roofline(st, prec: str, n_nodes: int, nrhs: int, ms: float, coupling: str) -> dict:
+    """The whole apply against its own roofline: its algorithmic bytes at
+    8 TB/s or its MFMA flops at the precision's dense peak, whichever takes
+    longer.  Flops: 2 per entry and column of every block the apply
+    multiplies (coupling, exact blocks, both leaf bases); bytes as
+    apply_alg_bytes."""
+    elem = 8 if prec == "fp64" else 4
+    b = apply_alg_bytes(st, elem, n_nodes, nrhs)
+    entries = st.coupling_entries + st.near_entries + st.dense_far_entries + 2 * n_nodes * st.k
+    f = 2.0 * entries * nrhs
+    peak = MFMA_PEAK_TFS["fp64" if prec == "fp64" else "fp32"]
+    t_b, t_f = b / HBM_PEAK_GBS / 1e6, f / peak / 1e9
+    return {"alg_bytes": b, "alg_flops": f, "hbm_ms": round(t_b, 4), "mfma_ms": round(t_f, 4),
+            "bound": "hbm" if t_b >= t_f else "mfma", "roofline_ms": round(max(t_b, t_f), 4),
+            "frac": round(max(t_b, t_f) / ms, 4)}
+
+
+def rel_err(a, ref) -> float:
+    """Largest relative l2 error over the right-hand sides (rows)."""
+    return float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)):.3e}")
+
+
+def other_workload(name: str, configs, steps: int = 10, warmup: int = 2, dense_rows=None) -> dict:
+    """Time and check the named workload in each (precision, coupling,
+    dense_far_max) of `configs` with its own right-hand sides; each result
+    against the FP64 result of the same operator, and against exact dense rows
+    when given (rows, values)."""
+    import torch
+
+    from paper_1811_05731_amd import h2dlp
+    case, xyz, tri = workload(name)
+    n = xyz.shape[0]
+    u1, rhs_text = case_rhs(case, xyz)
+    d1 = torch.tensor(u1, device="cuda:0")
+    d2 = torch.empty_like(d1)
+    res, outs = {"workload": describe(case, n, tri.shape[0], rhs_text), "nodes": n, "rhs": u1.shape[0]}, {}
+    for prec, cpl, dmax in configs:
+        op = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
+                            coupling=cpl, dense_far_max=dmax)
+        ms, _ = time_path(op, d1, d2, steps, warmup, None)
+        outs[(prec, cpl, dmax)] = d2.cpu().numpy()
+        res[f"{prec}_{cpl}_{dmax}"] = {"value": round(n * u1.shape[0] / (ms * 1e-3) / 1e9, 4),
+                                      "ms_per_step": round(ms, 4),
+                                      "resident_GB": round(op.stats.bytes_resident / 1e9, 3)}
+        op.close()
+    for (prec, cpl, dmax), val in outs.items():
+        rec = res[f"{prec}_{cpl}_{dmax}"]
+        ref = next((v for (p, c, d), v in outs.items() if p == "fp64" and d == dmax), None)
+        if ref is not None and prec != "fp64":
+            rec["vs_fp64_gpu_rel_err"] = rel_err(val, ref)
+        if dense_rows is not None:
+            rows, vals = dense_rows
+            rec["vs_dense_rows_rel_err"] = [float(f"{e:.3e}") for e in
+                                            np.linalg.norm(val[:, rows] - vals, axis=1) / np.linalg.norm(vals, axis=1)]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -380,7 +538,9 @@ def main():
                     help="admissible blocks with |t||s| <= this are stored exactly (0: the plain H2 matrix; "
                          "-1: where that is cheaper -- k^2 with stored coupling, k^2/2 with generated coupling)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-cpu-c2", action="store_true", help="skip the direct oracle apply at 163842 nodes")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and coupling modes")
+    ap.add_argument("--no-workloads", action="store_true", help="skip the 163842-node sphere and the film")
     ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
     args = ap.parse_args()
@@ -407,9 +567,9 @@ def main():
     def dmax_of(coupling):
         return args.dense_far_max if args.dense_far_max >= 0 else default_dense_far_max(case.order, coupling)
 
-    def build(prec, coupling):
+    def build(prec, coupling, dmax=None):
         return h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
-                              coupling=coupling, dense_far_max=dmax_of(coupling))
+                              coupling=coupling, dense_far_max=dmax_of(coupling) if dmax is None else dmax)
 
     t0 = time.perf_counter()
     op = build(args.precision, args.coupling)
@@ -454,6 +614,7 @@ def main():
                    "precision": args.precision, "coupling": args.coupling, "dense_far_max": dense_far_max},
         "roofline": roof,
         "rooflines": rooflines,
+        "apply_roofline": apply_roofline(st, args.precision, n, nrhs, ms, args.coupling),
         "apply_hbm_frac": round(b_apply / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "copy_GBps": None,
         "apply_alg_bytes": b_apply,
@@ -474,25 +635,31 @@ def main():
     out["apply_copy_frac"] = round(b_apply / (ms * 1e-3) / 1e9 / copy_gbs, 4)
 
     if not args.no_variants:
+        print("# other precisions and representations", file=sys.stderr, flush=True)
         variants, outs = {}, {}
-        configs = [("fp64", "stored"), ("fp64", "generated"), ("fp32", "stored"), ("fp32", "generated"),
-                   ("bf16x3", "stored"), ("bf16x6", "stored")]
-        for prec, cpl in configs:
-            if (prec, cpl) == (args.precision, args.coupling):
+        # each in the benchmark's configuration of its coupling mode, and the
+        # plain interpolation H2 matrix (no exact admissible blocks)
+        configs = [("fp64", "stored", None), ("fp64", "generated", None), ("fp32", "stored", None),
+                   ("fp32", "generated", None), ("bf16x3", "stored", None), ("bf16x6", "stored", None),
+                   ("fp64", "generated", 0), ("fp32", "generated", 0), ("bf16x3", "stored", 0)]
+        for prec, cpl, dm in configs:
+            dmax = dmax_of(cpl) if dm is None else dm
+            if (prec, cpl, dmax) == (args.precision, args.coupling, dense_far_max):
                 continue
             if (prec.startswith("bf16") or cpl == "generated") and case.order > 5:
                 continue
-            opv = build(prec, cpl)
+            opv = build(prec, cpl, dmax)
             msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=("coupling",))
-            key = prec if cpl == "stored" else f"{prec}_generated"
+            key = (prec if cpl == "stored" else f"{prec}_generated") + ("_plain" if dm == 0 and dmax == 0 else "")
             outs[key] = d_u2.cpu().numpy()
             ev = 8 if prec == "fp64" else 4
             variants[key] = {"value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
-                             "dense_far_max": dmax_of(cpl),
+                             "dense_far_max": dmax,
                              "coupling": roofline_of(opv.stats, prec, cpl, kv, n),
                              "resident_GB": round(opv.stats.bytes_resident / 1e9, 2),
                              "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9
-                                                     / HBM_PEAK_GBS, 4)}
+                                                     / HBM_PEAK_GBS, 4),
+                             "apply_roofline": apply_roofline(opv.stats, prec, n, nrhs, msv, cpl)}
             opv.close()
         # each result against the FP64 result of the same operator (the same
         # exact-block threshold: both coupling modes give the same operator)
@@ -505,21 +672,37 @@ def main():
 
         def rel(a, dmax):
             ref = fp64_by_dmax.get(dmax)
+            return None if ref is None else rel_err(a, ref)
+
+        def rel_k(a, dmax):
+            # the same error relative to |K u1| (without the diagonal)
+            ref = fp64_by_dmax.get(dmax)
             if ref is None:
                 return None
-            return float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(ref, axis=1)):.3e}")
-
-        ref = fp64_by_dmax.get(dense_far_max)
-        if ref is not None and args.precision != "fp64":
-            out["vs_fp64_gpu_rel_err"] = rel(u2_main, dense_far_max)
-            # the same error relative to |K u1| (the far-reaching part, without the diagonal)
             k_ref = ref - diag_main[None, :] * u1
-            out["vs_fp64_gpu_rel_err_of_K"] = float(
-                f"{np.max(np.linalg.norm(u2_main - ref, axis=1) / np.linalg.norm(k_ref, axis=1)):.3e}")
+            return float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(k_ref, axis=1)):.3e}")
+
+        if args.precision != "fp64":
+            out["vs_fp64_gpu_rel_err"] = rel(u2_main, dense_far_max)
+            out["vs_fp64_gpu_rel_err_of_K"] = rel_k(u2_main, dense_far_max)
         for key, val in outs.items():
             if fp64_by_dmax.get(variants[key]["dense_far_max"]) is not val:
                 variants[key]["vs_fp64_gpu_rel_err"] = rel(val, variants[key]["dense_far_max"])
+                variants[key]["vs_fp64_gpu_rel_err_of_K"] = rel_k(val, variants[key]["dense_far_max"])
         out["variants"] = variants
+
+    if not args.no_workloads and args.workload == "sphere_l8":
+        print("# the 163842-node sphere and the film", file=sys.stderr, flush=True)
+        g = np.load(os.path.join(ROOT, "tests", "golden", "sphere_l7_dense_rows.npz"))
+        c2 = workload("sphere_l7")[0]
+        k2 = c2.order ** 6
+        out["sphere_l7"] = other_workload("sphere_l7", [("fp32", "generated", k2 // 2), ("fp64", "generated", k2 // 2),
+                                                        ("fp32", "stored", 0), ("fp64", "stored", 0)],
+                                          dense_rows=(g["rows"], g["values"]))
+        c3 = workload("film")[0]
+        k2 = c3.order ** 6
+        out["film"] = other_workload("film", [("fp32", "generated", k2 // 2), ("fp64", "generated", k2 // 2),
+                                              ("fp32", "stored", 0), ("fp64", "stored", 0)])
 
     if not args.no_serve:
         print("# serving the mixed request stream", file=sys.stderr, flush=True)
@@ -536,8 +719,8 @@ def main():
         out["copy_calibration_bytes"] = a.numel() * 4
 
     if not args.no_cpu:
-        print("# timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(xyz, tri, case, nrhs)
+        print("# timing the CPU oracle", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(xyz, tri, case, nrhs, dense_far_max, direct_c2=not args.no_cpu_c2)
     print(json.dumps(out), flush=True)
 
 

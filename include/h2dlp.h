@@ -77,7 +77,16 @@ typedef struct {
  * stored as its exact entries (Section 3, like an inadmissible block) instead
  * of through the cluster bases and a k x k coupling matrix: cheaper when
  * |t| |s| is small against k^2, and exact.  0 keeps every admissible block
- * low-rank (the plain H2 matrix). */
+ * low-rank (the plain H2 matrix).
+ * recompress_eps: 0 keeps the interpolation bases.  In (0, 1) the build
+ * recompresses the matrix algebraically (Section 4: the conversion to an H2
+ * matrix whose ranks follow the accuracy): the row and column bases become
+ * orthonormal nested bases of adaptive rank, from SVDs of each cluster's
+ * basis weighted by every low-rank block it serves, truncated at
+ * recompress_eps times the cluster's largest singular value, and every
+ * coupling matrix is projected onto them and stored (r_t x r_s).  FP64 and
+ * FP32, stored coupling, order <= 5 (else ENOTSUP).  h2dlp_plan reports the
+ * interpolation sizes (an upper bound); the ranks are known after the build. */
 typedef struct {
     int    order;
     int    leaf;
@@ -88,6 +97,7 @@ typedef struct {
     void*  stream;
     int    coupling;
     int64_t dense_far_max;
+    double recompress_eps;
 } h2dlp_options;
 
 #define H2DLP_COUPLING_STORED     0
@@ -102,7 +112,7 @@ typedef struct {
     int32_t depth;              /* deepest cluster level (root = 0) */
     int64_t n_clusters, n_leaves;
     int64_t n_far, n_near;      /* low-rank admissible blocks, inadmissible leaf blocks */
-    int64_t coupling_entries;   /* n_far * k * k */
+    int64_t coupling_entries;   /* n_far * k * k (sum of r_t r_s when recompressed) */
     int64_t near_entries;       /* sum over near blocks of |t| |s| */
     int64_t nearsing_entries;   /* near-singular entries kept in FP64 (all but FP64) */
     int64_t bytes_coupling, bytes_near, bytes_bases, bytes_transfer, bytes_other;
@@ -111,10 +121,13 @@ typedef struct {
     double  compression;        /* 1 - (H2 bytes)/(8 N^2), the paper's ratio r (Section 6.1) */
     int64_t n_far_dense;        /* admissible blocks stored as exact entries (dense_far_max) */
     int64_t dense_far_entries;  /* their entries (counted in bytes_near, not in near_entries) */
+    int64_t rank_sum_row;       /* sum over clusters of the row / column basis ranks (k each */
+    int64_t rank_sum_col;       /*   without recompression)                                 */
+    int32_t rank_max_row, rank_max_col;
 } h2dlp_stats;
 
 /* Fill *opt with defaults: order 4, leaf 32, eta 2, FP64, alpha 0.1, device -1,
- * stream NULL, coupling STORED, dense_far_max 0. */
+ * stream NULL, coupling STORED, dense_far_max 0, recompress_eps 0. */
 void h2dlp_default_options(h2dlp_options* opt);
 
 /* Build the H2 operator for `mesh` (copied; the caller may free it on return).
@@ -140,15 +153,18 @@ int h2dlp_plan(const h2dlp_mesh* mesh, const h2dlp_options* opt, h2dlp_handle* o
  * (nrhs, n_nodes) row-major, one contiguous vector per right-hand side, in the
  * caller's node order; must not overlap.  Asynchronous on the null stream, using
  * the handle's own workspace (not safe to call concurrently on one handle).
- * Errors: EINVAL (NULL, nrhs < 1), EDEVICE. */
+ * Errors: EINVAL (NULL, nrhs < 1, u1 or u2 not device memory of the handle's
+ * GPU or ending before nrhs * n_nodes values), EDEVICE. */
 int h2dlp_apply(h2dlp_handle h, const double* u1, double* u2, int nrhs);
 
 /* As h2dlp_apply, with io_dtype (H2DLP_IO_F64 / H2DLP_IO_F32), a hipStream_t
  * (NULL = null stream) and a caller-owned device workspace of at least
  * h2dlp_stats.workspace_bytes (NULL = the handle's own).  Distinct workspaces
  * make concurrent applies of one handle on different streams safe.  Right-hand
- * sides are processed 16 at a time.  Errors: EINVAL, ENOMEM (workspace_bytes
- * too small), EDEVICE. */
+ * sides are processed 16 at a time.  Errors: EINVAL (as h2dlp_apply; also a
+ * workspace that is not device memory of the handle's GPU or whose allocation
+ * ends before h2dlp_stats.workspace_bytes), ENOMEM (workspace_bytes too small),
+ * EDEVICE. */
 int h2dlp_apply_ex(h2dlp_handle h, const void* u1, void* u2, int nrhs, int io_dtype,
                    void* stream, void* workspace, size_t workspace_bytes);
 

@@ -47,7 +47,8 @@ def build(verbose: bool = False) -> str:
         for src, extra in (("structure.cpp", ["-ffp-contract=off", "-x", "c++"]),
                            ("api.cpp", ["-x", "c++"]),
                            ("build_kernels.hip", []),
-                           ("apply_kernels.hip", [])):
+                           ("apply_kernels.hip", []),
+                           ("recompress.hip", [])):
             obj = os.path.join(tmp, src + ".o")
             cmd = [hipcc, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
             if src.endswith(".cpp"):
@@ -63,7 +64,8 @@ def build(verbose: bool = False) -> str:
             if verbose and out.strip():
                 print(out)
         tmp_lib = LIB + ".tmp"
-        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp_lib, *objs])
+        _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp_lib, *objs,
+              "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
         os.replace(tmp_lib, LIB)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)

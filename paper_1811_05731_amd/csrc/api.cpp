@@ -11,7 +11,9 @@
 #include <vector>
 
 #include "../../include/h2dlp.h"
+#include "entry.h"
 #include "kernels.h"
+#include "recompress.h"
 #include "structure.h"
 
 using namespace h2dlp;
@@ -146,8 +148,11 @@ struct h2dlp_ctx {
     bool offloaded = false;
     struct Parked { void** field; void* host; size_t bytes; bool scratch; };
     std::vector<bool> empty_field;   // fields() entries that hold no bytes (NULL after the build)
-    // the near field runs on this stream while the far-field chain runs on the caller's
+    // the near field runs on this stream while the far-field chain runs on the caller's;
+    // fork and join order it against the caller's stream (created once: an apply
+    // creates no event)
     hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     // a reload enqueued on a stream: every later use of the device buffers waits for it
     hipEvent_t ready = nullptr;
     bool ready_pending = false;
@@ -167,7 +172,25 @@ struct h2dlp_ctx {
     std::vector<NearDesc> nears;
     std::vector<ItemDesc> items_fwd, items_cpl, items_leaf, items_near, items_v;
     std::vector<BlkDesc> blks_fwd, blks_cpl, blks_leaf;
-    int64_t off_wt = 0, off_s = 0, off_l = 0;
+    int64_t off_wt = 0, off_s = 0, off_l = 0, off_v = 0;
+    // algebraic recompression (recompress_eps > 0): adaptive ranks of the row
+    // and column bases; x^ rows of cluster g start at xo[g] (column ranks),
+    // y^ rows at yo[g] (row ranks); the transfers have their own pools and
+    // per-level item ranges
+    bool rec = false;
+    std::vector<int32_t> far_t, far_s;
+    std::vector<int32_t> rank_row, rank_col;
+    void* d_pool_up = nullptr;
+    void* d_pool_down = nullptr;
+    void* d_pool_q = nullptr;
+    ItemDesc* d_items_up = nullptr;
+    BlkDesc* d_blks_up = nullptr;
+    ItemDesc* d_items_down = nullptr;
+    BlkDesc* d_blks_down = nullptr;
+    BlkDesc* d_blks_v = nullptr;
+    std::vector<int32_t> up_off, up_end, down_off;   // item ranges by level: [up_off[l], up_end[l]),
+                                                     // [down_off[l], down_off[l + 1])
+    int32_t rt_fwd = 1, rt_up = 1, rt_cpl = 1, rt_down = 1;
     h2dlp_stats st{};
     // profiling
     int prof = 0;                    // bit q: record launches of kind q
@@ -184,6 +207,8 @@ struct h2dlp_ctx {
         for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         if (ready) { (void)hipEventSynchronize(ready); (void)hipEventDestroy(ready); }
         if (side) { (void)hipStreamSynchronize(side); (void)hipStreamDestroy(side); }
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
         for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
         for (auto& p : parked) if (p.host) (void)hipHostFree(p.host);
         (void)hipSetDevice(cur);
@@ -200,7 +225,10 @@ struct h2dlp_ctx {
                 {(void**)&d_items_cpl, false}, {(void**)&d_blks_cpl, false}, {(void**)&d_items_leaf, false},
                 {(void**)&d_blks_leaf, false}, {(void**)&d_items_near, false}, {(void**)&d_items_v, false},
                 {(void**)&d_ns_off, false}, {(void**)&d_ns_pos, false},
-                {(void**)&d_ns_val, false}, {(void**)&d_ws, true}};
+                {(void**)&d_ns_val, false}, {(void**)&d_pool_up, false}, {(void**)&d_pool_down, false},
+                {(void**)&d_pool_q, false}, {(void**)&d_items_up, false}, {(void**)&d_blks_up, false},
+                {(void**)&d_items_down, false}, {(void**)&d_blks_down, false}, {(void**)&d_blks_v, false},
+                {(void**)&d_ws, true}};
     }
     size_t bytes_of(void* p) const {
         for (const auto& b : bufs) if (b.p == p) return b.bytes;
@@ -253,6 +281,8 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     h->elem = h->prec == H2DLP_FP64 ? 8 : 4;
     h->elem_s = h->prec == H2DLP_BF16X6 ? 6 : h->elem;
     const bool fp64 = h->prec == H2DLP_FP64;
+    const bool rec = o->recompress_eps > 0.0;
+    h->rec = rec;
 
     std::string err = build_structure(h->S, mesh->xyz, mesh->n_nodes, mesh->tri, mesh->n_tris, o->leaf, o->eta,
                                       o->alpha, !fp64);
@@ -334,6 +364,10 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         std::sort(lst.begin(), lst.end());
         h->items_cpl.push_back(ItemDesc{g * k, k, int32_t(h->blks_cpl.size()), int32_t(h->blks_cpl.size() + lst.size())});
         for (int32_t s : lst) {
+            if (rec) {                   // low-rank pairs, in this order; layouts follow the ranks
+                h->far_t.push_back(g);
+                h->far_s.push_back(s);
+            }
             if (gen) {                   // nothing stored: a_off names the source cluster
                 h->blks_cpl.push_back(BlkDesc{int64_t(s), k, s * k});
                 continue;
@@ -359,18 +393,25 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         }
     }
     h->vleaves.resize(leaf_pre.size());
-    int64_t off_l = 0, near_entries = 0;
+    int64_t off_l = 0, off_v = 0, near_entries = 0;
     for (size_t q = 0; q < leaf_pre.size(); ++q) {
         const int32_t t = leaf_pre[q];
         const Cluster& X = S.cl[t];
         auto& lst = near_by_t[t];
         std::sort(lst.begin(), lst.end(), [&](int32_t a, int32_t b) { return S.cl[a].begin < S.cl[b].begin; });
-        h->items_leaf.push_back(ItemDesc{int32_t(X.begin), int32_t(X.size()), int32_t(h->blks_leaf.size()),
-                                         int32_t(h->blks_leaf.size() + 1 + lst.size())});
-        off_l = align_block(off_l);
-        h->vleaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), h->gid_of_pre[t], 0, off_l};
-        h->blks_leaf.push_back(BlkDesc{off_l, k, SRC1 | (h->gid_of_pre[t] * k)});
-        off_l += int64_t(X.size()) * k;
+        const int32_t b0 = int32_t(h->blks_leaf.size());
+        h->items_leaf.push_back(ItemDesc{int32_t(X.begin), int32_t(X.size()), b0,
+                                         int32_t(b0 + (rec ? 0 : 1) + lst.size())});
+        if (rec) {           // V_t in FP64 for the recompression only, in a pool of the build
+            off_v = align_block(off_v);
+            h->vleaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), h->gid_of_pre[t], 0, off_v};
+            off_v += int64_t(X.size()) * k;
+        } else {
+            off_l = align_block(off_l);
+            h->vleaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), h->gid_of_pre[t], 0, off_l};
+            h->blks_leaf.push_back(BlkDesc{off_l, k, SRC1 | (h->gid_of_pre[t] * k)});
+            off_l += int64_t(X.size()) * k;
+        }
         for (int32_t s : lst) {
             const Cluster& Y = S.cl[s];
             off_l = align_block(off_l);
@@ -384,8 +425,8 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     h->n_items_cpl = int32_t(h->items_cpl.size());
     h->n_items_leaf = int32_t(h->items_leaf.size());
     for (const ItemDesc& d : h->items_leaf) {     // block 0 of a leaf item is V_t, the rest near blocks
-        h->items_near.push_back(ItemDesc{d.out_row, d.m, d.blk_begin + 1, d.blk_end});
-        h->items_v.push_back(ItemDesc{d.out_row, d.m, d.blk_begin, d.blk_begin + 1});
+        h->items_near.push_back(ItemDesc{d.out_row, d.m, d.blk_begin + (rec ? 0 : 1), d.blk_end});
+        if (!rec) h->items_v.push_back(ItemDesc{d.out_row, d.m, d.blk_begin, d.blk_begin + 1});
     }
     // near-field items in node (depth-first) order rather than level order:
     // neighbouring items, dealt to one XCD in chunks, are then neighbouring
@@ -393,6 +434,7 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     std::stable_sort(h->items_near.begin(), h->items_near.end(),
                      [](const ItemDesc& a, const ItemDesc& b) { return a.out_row < b.out_row; });
     h->rt_leaf = (o->leaf + 15) / 16;
+    h->off_v = off_v;
     h->off_wt = off_wt;
     h->off_s = off_s;
     h->off_l = off_l;
@@ -447,7 +489,195 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
                         st.workspace_bytes + (fp64 ? 0 : int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8)));
     const double h2_bytes = double(st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer);
     st.compression = 1.0 - h2_bytes / (8.0 * double(N) * double(N));
+    st.rank_sum_row = st.rank_sum_col = int64_t(C) * k;     // the interpolation ranks (an upper bound
+    st.rank_max_row = st.rank_max_col = k;                  //   when recompressed: set by the build)
     return H2DLP_OK;
+}
+
+int32_t row_tiles(const std::vector<int32_t>& r) {
+    int32_t mx = 1;
+    for (int32_t v : r) mx = std::max(mx, v);
+    return (mx + 15) / 16;
+}
+
+// The recompressed operator: ranks from the GPU recompression of the FP64
+// interpolation bases (wt64: W_s^T blocks at h->leaves, v64: V_t blocks at
+// h->vleaves), then every apply descriptor and pool laid out by those ranks.
+void recompress_impl(h2dlp_ctx* h, const double* d_boxes, const double* wt64, const double* v64, int64_t* kept,
+                     hipStream_t stream) {
+    const Structure& S = h->S;
+    const int k = h->k, m = h->m;
+    const int32_t C = h->n_clusters;
+    const size_t e = h->elem;
+    RecompressPlan P;
+    P.m = m;
+    P.k = k;
+    P.n_clusters = C;
+    P.depth = S.depth;
+    P.level_off = h->level_off;
+    P.child0 = h->child0;
+    P.child1 = h->child1;
+    P.parent = h->parent;
+    P.leaf_n.assign(C, 0);
+    int maxleaf = 1;
+    for (const LeafDesc& L : h->leaves) { P.leaf_n[L.gid] = L.n; maxleaf = std::max(maxleaf, int(L.n)); }
+    P.rows = std::max(2 * k, maxleaf);
+    P.far_t = h->far_t;
+    P.far_s = h->far_s;
+    P.eps = h->opt.recompress_eps;
+    const int64_t rk = int64_t(P.rows) * k;
+
+    // leaf bases into per-cluster column-major slots
+    double* vslot = h->alloc<double>(sizeof(double) * size_t(C) * rk, nullptr);
+    double* wslot = h->alloc<double>(sizeof(double) * size_t(C) * rk, nullptr);
+    check(hipMemsetAsync(vslot, 0, sizeof(double) * size_t(C) * rk, stream), "clear");
+    check(hipMemsetAsync(wslot, 0, sizeof(double) * size_t(C) * rk, stream), "clear");
+    {
+        std::vector<GatherDesc> gv, gw;
+        for (const LeafDesc& L : h->vleaves) gv.push_back(GatherDesc{L.a_off, L.gid, L.n});
+        for (const LeafDesc& L : h->leaves) gw.push_back(GatherDesc{L.a_off, L.gid, L.n});
+        GatherDesc* dgv = h->upload(gv, nullptr, stream);
+        GatherDesc* dgw = h->upload(gw, nullptr, stream);
+        check(launch_gather_leaf_basis(dgv, int64_t(gv.size()), v64, k, P.rows, false, vslot, stream), "gather");
+        check(launch_gather_leaf_basis(dgw, int64_t(gw.size()), wt64, k, P.rows, true, wslot, stream), "gather");
+        check(hipStreamSynchronize(stream), "gather");
+        h->release(dgv);
+        h->release(dgw);
+    }
+    RecompressResult R;
+    std::string err = recompress(P, d_boxes, vslot, wslot, stream, &R);
+    h->release(vslot);
+    h->release(wslot);
+    if (!err.empty()) throw HipError{hipErrorUnknown, "recompression: " + err};
+    const std::vector<int32_t>& rr = R.rank_row;
+    const std::vector<int32_t>& rc = R.rank_col;
+    h->rank_row = rr;
+    h->rank_col = rc;
+    std::vector<int32_t> xo(C + 1, 0), yo(C + 1, 0);
+    for (int32_t g = 0; g < C; ++g) { xo[g + 1] = xo[g] + rc[g]; yo[g + 1] = yo[g] + rr[g]; }
+
+    // descriptors, pool offsets and the stores from the FP64 slots
+    std::vector<StoreDesc> st_wt, st_up, st_down, st_q;
+    std::vector<BlkDesc> blks_up, blks_down, blks_v;
+    std::vector<ItemDesc> items_up, items_down;
+    h->items_fwd.clear(); h->blks_fwd.clear(); h->items_cpl.clear(); h->blks_cpl.clear(); h->items_v.clear();
+    int64_t o_wt = 0, o_up = 0, o_s = 0, o_down = 0, o_q = 0;
+    double* Uc = R.u_col;
+    double* Ur = R.u_row;
+    for (const LeafDesc& L : h->leaves) {              // x^_s = Q'_s^T x|_s
+        const int32_t r = rc[L.gid];
+        if (r == 0) continue;
+        o_wt = align_block(o_wt);
+        h->items_fwd.push_back(ItemDesc{xo[L.gid], r, int32_t(h->blks_fwd.size()), int32_t(h->blks_fwd.size() + 1)});
+        h->blks_fwd.push_back(BlkDesc{o_wt, L.n, L.pos});
+        st_wt.push_back(StoreDesc{Uc + int64_t(L.gid) * rk, P.rows, r, L.n, 1, o_wt});
+        o_wt += int64_t(r) * L.n;
+    }
+    h->up_off.assign(S.depth + 2, 0);
+    h->up_end.assign(S.depth + 2, 0);
+    for (int l = S.depth; l >= 0; --l) {               // x^_t = sum_c F'_c^T x^_c (levels deepest first)
+        h->up_off[l] = int32_t(items_up.size());
+        for (int32_t g = h->level_off[l]; g < h->level_off[l + 1]; ++g) {
+            if (h->child0[g] < 0 || rc[g] == 0) continue;
+            const int32_t b0 = int32_t(blks_up.size());
+            for (int side = 0; side < 2; ++side) {
+                const int32_t c = side == 0 ? h->child0[g] : h->child1[g];
+                if (rc[c] == 0) continue;
+                o_up = align_block(o_up);
+                blks_up.push_back(BlkDesc{o_up, rc[c], xo[c]});
+                st_up.push_back(StoreDesc{Uc + int64_t(g) * rk + side * k, P.rows, rc[g], rc[c], 1, o_up});
+                o_up += int64_t(rc[g]) * rc[c];
+            }
+            items_up.push_back(ItemDesc{xo[g], rc[g], b0, int32_t(blks_up.size())});
+        }
+        h->up_end[l] = int32_t(items_up.size());
+    }
+    std::vector<int64_t> a_s(h->far_t.size(), 0);
+    for (size_t b = 0, g = 0; g < size_t(C); ++g) {    // y^_t = sum_s S'_ts x^_s
+        const int32_t b0 = int32_t(h->blks_cpl.size());
+        for (; b < h->far_t.size() && h->far_t[b] == int32_t(g); ++b) {
+            const int32_t s = h->far_s[b];
+            if (rr[g] == 0 || rc[s] == 0) continue;
+            o_s = align_block(o_s);
+            a_s[b] = o_s;
+            h->blks_cpl.push_back(BlkDesc{o_s, rc[s], xo[s]});
+            o_s += int64_t(rr[g]) * rc[s];
+        }
+        if (rr[g] > 0) h->items_cpl.push_back(ItemDesc{yo[g], rr[g], b0, int32_t(h->blks_cpl.size())});
+    }
+    h->down_off.assign(S.depth + 2, 0);
+    for (int l = 0; l <= S.depth; ++l) {               // y^_c += F_c y^_parent
+        h->down_off[l] = int32_t(items_down.size());
+        for (int32_t c = h->level_off[l]; c < h->level_off[l + 1]; ++c) {
+            const int32_t p = h->parent[c];
+            if (p < 0 || rr[c] == 0 || rr[p] == 0) continue;
+            o_down = align_block(o_down);
+            items_down.push_back(ItemDesc{yo[c], rr[c], int32_t(blks_down.size()), int32_t(blks_down.size() + 1)});
+            blks_down.push_back(BlkDesc{o_down, rr[p], yo[p]});
+            st_down.push_back(StoreDesc{Ur + int64_t(p) * rk + (c == h->child1[p] ? k : 0), P.rows, rr[c], rr[p], 0,
+                                        o_down});
+            o_down += int64_t(rr[c]) * rr[p];
+        }
+        h->down_off[l + 1] = int32_t(items_down.size());
+    }
+    for (const LeafDesc& L : h->vleaves) {             // y|_t += Q_t y^_t
+        const int32_t r = rr[L.gid];
+        if (r == 0) continue;
+        o_q = align_block(o_q);
+        h->items_v.push_back(ItemDesc{L.pos, L.n, int32_t(blks_v.size()), int32_t(blks_v.size() + 1)});
+        blks_v.push_back(BlkDesc{o_q, r, SRC1 | yo[L.gid]});
+        st_q.push_back(StoreDesc{Ur + int64_t(L.gid) * rk, P.rows, L.n, r, 0, o_q});
+        o_q += int64_t(L.n) * r;
+    }
+    h->d_pool_wt = h->alloc<void>(e * size_t(std::max<int64_t>(o_wt, 1)), kept);
+    h->d_pool_up = h->alloc<void>(e * size_t(std::max<int64_t>(o_up, 1)), kept);
+    h->d_pool_s = h->alloc<void>(e * size_t(std::max<int64_t>(o_s, 1)), kept);
+    h->d_pool_down = h->alloc<void>(e * size_t(std::max<int64_t>(o_down, 1)), kept);
+    h->d_pool_q = h->alloc<void>(e * size_t(std::max<int64_t>(o_q, 1)), kept);
+    for (auto* list : {&st_wt, &st_up, &st_down, &st_q}) {
+        void* pool = list == &st_wt ? h->d_pool_wt : list == &st_up ? h->d_pool_up
+                   : list == &st_down ? h->d_pool_down : h->d_pool_q;
+        if (list->empty()) continue;
+        StoreDesc* d = h->upload(*list, nullptr, stream);
+        check(launch_store_layout(d, int64_t(list->size()), h->prec, pool, stream), "store bases");
+        check(hipStreamSynchronize(stream), "store bases");
+        h->release(d);
+    }
+    err = recompress_couplings(P, d_boxes, R, a_s, h->prec, h->d_pool_s, stream);
+    R.release();
+    if (!err.empty()) throw HipError{hipErrorUnknown, "recompression: " + err};
+    h->d_items_fwd = h->upload(h->items_fwd, kept, stream);
+    h->d_blks_fwd = h->upload(h->blks_fwd, kept, stream);
+    h->d_items_up = h->upload(items_up, kept, stream);
+    h->d_blks_up = h->upload(blks_up, kept, stream);
+    h->d_items_cpl = h->upload(h->items_cpl, kept, stream);
+    h->d_blks_cpl = h->upload(h->blks_cpl, kept, stream);
+    h->d_items_down = h->upload(items_down, kept, stream);
+    h->d_blks_down = h->upload(blks_down, kept, stream);
+    h->d_items_v = h->upload(h->items_v, kept, stream);
+    h->d_blks_v = h->upload(blks_v, kept, stream);
+    h->n_items_fwd = int32_t(h->items_fwd.size());
+    h->n_items_cpl = int32_t(h->items_cpl.size());
+    h->rt_fwd = row_tiles(rc);
+    h->rt_up = row_tiles(rc);
+    h->rt_cpl = row_tiles(rr);
+    h->rt_down = row_tiles(rr);
+    // workspace and sizes with the ranks found
+    h->ws_xh = align_up(e * size_t(std::max({xo[C], yo[C], 1})) * RHS_TILE);
+    h->ws_bytes = h->ws_x + h->ws_x64 + h->ws_y64 + 2 * h->ws_xh;
+    h2dlp_stats& st = h->st;
+    st.coupling_entries = 0;
+    for (size_t b = 0; b < h->far_t.size(); ++b) st.coupling_entries += int64_t(rr[h->far_t[b]]) * rc[h->far_s[b]];
+    st.bytes_coupling = int64_t(e) * st.coupling_entries;
+    st.bytes_bases = int64_t(e) * (o_wt + o_q);
+    st.bytes_transfer = int64_t(e) * (o_up + o_down);
+    st.workspace_bytes = int64_t(h->ws_bytes);
+    st.rank_sum_row = yo[C];
+    st.rank_sum_col = xo[C];
+    st.rank_max_row = *std::max_element(rr.begin(), rr.end());
+    st.rank_max_col = *std::max_element(rc.begin(), rc.end());
+    const double h2_bytes = double(st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer);
+    st.compression = 1.0 - h2_bytes / (8.0 * double(S.n_nodes) * double(S.n_nodes));
 }
 
 // Device part of a build: upload, generate every block in FP64 arithmetic, free the build-only arrays.
@@ -468,20 +698,27 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_parent = h->upload(h->parent, &kept, stream);
     h->d_front = h->upload(h->down_front, &kept, stream);
     h->d_diag = h->alloc<double>(sizeof(double) * N, &kept);
-    h->d_e = h->alloc<void>(e * size_t(C) * 3 * m * m, &kept);
-    h->d_pool_wt = h->alloc<void>(e * size_t(h->off_wt), &kept);
-    h->d_pool_s = h->alloc<void>(h->elem_s * size_t(h->off_s), &kept);
+    const bool rec = h->rec;
+    // recompression: the interpolation bases are built in FP64 for it alone;
+    // transfers, couplings and the new bases follow the ranks it finds
+    if (!rec) {
+        h->d_e = h->alloc<void>(e * size_t(C) * 3 * m * m, &kept);
+        h->d_pool_wt = h->alloc<void>(e * size_t(h->off_wt), &kept);
+        h->d_pool_s = h->alloc<void>(h->elem_s * size_t(h->off_s), &kept);
+        h->d_items_fwd = h->upload(h->items_fwd, &kept, stream);
+        h->d_blks_fwd = h->upload(h->blks_fwd, &kept, stream);
+        h->d_items_cpl = h->upload(h->items_cpl, &kept, stream);
+        h->d_blks_cpl = h->upload(h->blks_cpl, &kept, stream);
+        h->d_items_v = h->upload(h->items_v, &kept, stream);
+    }
     h->d_pool_leaf = h->alloc<void>(e * size_t(h->off_l), &kept);
-    h->d_items_fwd = h->upload(h->items_fwd, &kept, stream);
-    h->d_blks_fwd = h->upload(h->blks_fwd, &kept, stream);
-    h->d_items_cpl = h->upload(h->items_cpl, &kept, stream);
     if (!h->cgeo.empty()) h->d_cgeo = h->upload(h->cgeo, &kept, stream);
-    h->d_blks_cpl = h->upload(h->blks_cpl, &kept, stream);
     h->d_items_leaf = h->upload(h->items_leaf, &kept, stream);
     h->d_blks_leaf = h->upload(h->blks_leaf, &kept, stream);
     h->d_items_near = h->upload(h->items_near, &kept, stream);
-    h->d_items_v = h->upload(h->items_v, &kept, stream);
     check(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "side stream");
+    check(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming), "event");
+    check(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming), "event");
     {
         int dev = 0, lds_cu = 0, lds_wg = 0;
         check(hipGetDevice(&dev), "device");
@@ -515,12 +752,22 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     DevMesh dm{d_xyz, d_tri, d_inc_off, d_inc_tri, d_inc_loc, d_tgeo, h->d_perm};
     check(launch_tri_geometry(d_xyz, d_tri, T, d_tgeo, stream), "triangle geometry");
     check(launch_diagonal(dm, N, h->d_diag, stream), "diagonal");
-    check(launch_build_wt(dm, d_boxes, m, d_quad, int(quad.size() / 3), d_leaves, int64_t(h->leaves.size()), h->prec,
-                          h->d_pool_wt, stream), "column basis");
-    check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf, stream),
-          "row basis");
-    check(launch_build_transfer(d_boxes, h->d_parent, C, m, h->prec, h->d_e, stream), "transfer");
-    if (h->d_cgeo == nullptr)
+    if (rec) {
+        double* wt64 = tmp(h->alloc<double>(sizeof(double) * size_t(h->off_wt), &scratch));
+        double* v64 = tmp(h->alloc<double>(sizeof(double) * size_t(h->off_v), &scratch));
+        check(launch_build_wt(dm, d_boxes, m, d_quad, int(quad.size() / 3), d_leaves, int64_t(h->leaves.size()),
+                              P_FP64, wt64, stream), "column basis");
+        check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), P_FP64, v64, stream),
+              "row basis");
+        recompress_impl(h, d_boxes, wt64, v64, &kept, stream);
+    } else {
+        check(launch_build_wt(dm, d_boxes, m, d_quad, int(quad.size() / 3), d_leaves, int64_t(h->leaves.size()),
+                              h->prec, h->d_pool_wt, stream), "column basis");
+        check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf, stream),
+              "row basis");
+        check(launch_build_transfer(d_boxes, h->d_parent, C, m, h->prec, h->d_e, stream), "transfer");
+    }
+    if (h->d_cgeo == nullptr && !rec)
         check(launch_build_coupling(d_boxes, m, h->kp, d_far, int64_t(h->fars.size()), h->prec, h->d_pool_s, stream),
               "coupling");
     check(launch_build_near(dm, d_near, int64_t(h->nears.size()), h->prec, h->d_pool_leaf,
@@ -530,6 +777,7 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     check(hipStreamSynchronize(stream), "build synchronize");
     for (void* p : temp) h->release(p);
     h->d_ws = h->alloc<void>(h->ws_bytes, &kept);
+    if (rec) h->st.bytes_resident = kept;
     h->empty_field.clear();
     for (auto& f : h->fields()) h->empty_field.push_back(*f.first == nullptr);
     // host-side descriptors are no longer needed
@@ -542,6 +790,38 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
 }
 
 h2dlp_ctx* as_ctx(h2dlp_handle h) { return reinterpret_cast<h2dlp_ctx*>(h); }
+
+// The kernels dereference u1, u2 and the workspace.  Refuse a pointer that is
+// not device memory of the handle's GPU, or whose allocation ends before
+// `bytes` from it, so that a wrong argument is an error and not a fault.
+bool device_range_ok(const void* p, size_t bytes, int dev, const char* name, std::string* why) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        *why = std::string(name) + " is not HIP device memory";
+        return false;
+    }
+    if (a.type != hipMemoryTypeDevice && a.type != hipMemoryTypeManaged) {
+        *why = std::string(name) + " is host memory, not device memory";
+        return false;
+    }
+    if (a.device != dev) {
+        *why = std::string(name) + " is on device " + std::to_string(a.device) + ", the operator on device " +
+               std::to_string(dev);
+        return false;
+    }
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) != hipSuccess) {
+        (void)hipGetLastError();       // no range for this kind of allocation: nothing more to check
+        return true;
+    }
+    if (static_cast<const char*>(p) + bytes > static_cast<const char*>(base) + size) {
+        *why = std::string(name) + ": its allocation ends before the " + std::to_string(bytes) + " bytes the call needs";
+        return false;
+    }
+    return true;
+}
 
 void rec_begin(h2dlp_ctx* h, hipStream_t s, int kind, hipEvent_t* a) {
     if (!(h->prof >> kind & 1)) return;
@@ -594,15 +874,23 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         check(launch_permute(u1p, io, N, nr, h->d_iperm, x, h->ws_x64 ? x64 : nullptr, prec, s), "permute");
         rec_end(h, s, 0, ev);
 
-        ProductArgs fwd{h->d_items_fwd, h->n_items_fwd, (k + 15) / 16, h->d_blks_fwd, h->d_pool_wt, x, nullptr, xh};
+        ProductArgs fwd{h->d_items_fwd, h->n_items_fwd, h->rec ? h->rt_fwd : (k + 15) / 16, h->d_blks_fwd,
+                        h->d_pool_wt, x, nullptr, xh};
         rec_begin(h, s, 1, &ev);
         check(launch_product_store(fwd, prec, true, s), "leaf forward");
         rec_end(h, s, 1, ev);
 
         for (int l = h->S.depth - 1; l >= 0; --l) {
             rec_begin(h, s, 2, &ev);
-            check(launch_upward(h->level_off[l], h->level_off[l + 1], h->d_child0, h->d_child1, h->d_e, xh, m, prec, s),
-                  "upward");
+            if (h->rec) {      // x^_t = sum_c F'_c^T x^_c, a grouped product per level
+                ProductArgs up{h->d_items_up + h->up_off[l], h->up_end[l] - h->up_off[l], h->rt_up, h->d_blks_up,
+                               h->d_pool_up, xh, nullptr, xh};
+                check(launch_product_store(up, prec, true, s), "upward");
+            } else {
+                check(launch_upward(h->level_off[l], h->level_off[l + 1], h->d_child0, h->d_child1, h->d_e, xh, m,
+                                    prec, s),
+                      "upward");
+            }
             rec_end(h, s, 2, ev);
         }
 
@@ -611,18 +899,18 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         // near field, diagonal and near-singular part into y64 on the side stream,
         // beside the coupling products (HBM-bound there, MFMA- or HBM-bound
         // here); forked after the latency-bound upward pass, which it would slow
-        hipEvent_t fork = nullptr, join = nullptr;
-        check(hipEventCreateWithFlags(&fork, hipEventDisableTiming), "event");
-        check(hipEventCreateWithFlags(&join, hipEventDisableTiming), "event");
-        check(hipEventRecord(fork, s), "event record");
-        check(hipStreamWaitEvent(h->side, fork, 0), "fork");
+        check(hipEventRecord(h->fork_ev, s), "event record");
+        check(hipStreamWaitEvent(h->side, h->fork_ev, 0), "fork");
         rec_begin(h, h->side, 6, &ev);
         check(launch_product_leaf(nearp, epi, prec, h->side), "near field");
         rec_end(h, h->side, 6, ev);
-        check(hipEventRecord(join, h->side), "event record");
+        check(hipEventRecord(h->join_ev, h->side), "event record");
 
         rec_begin(h, s, 3, &ev);
-        if (h->d_cgeo) {
+        if (h->rec) {
+            ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, h->rt_cpl, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
+            check(launch_product_store(cpl, prec, false, s), "coupling");
+        } else if (h->d_cgeo) {
             ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_cgeo, xh, nullptr, yh};
             check(launch_coupling_generated(cpl, m, prec, prec == P_FP32 && h->n_items_leaf > 0 ? h->cpl_lds : 0, s),
                   "coupling");
@@ -632,21 +920,34 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         }
         rec_end(h, s, 3, ev);
 
-        rec_begin(h, s, 4, &ev);
-        check(launch_downward_paths(int32_t(h->down_front.size()), h->d_front, h->d_parent, h->d_e, yh, m, prec, s),
-              "downward");
-        rec_end(h, s, 4, ev);
-        for (int l = h->down_l0 + 1; l <= h->S.depth; ++l) {
+        if (h->rec) {          // y^_c += F_c y^_parent, a grouped product per level
+            for (int l = 1; l <= h->S.depth; ++l) {
+                rec_begin(h, s, 4, &ev);
+                ProductArgs dn{h->d_items_down + h->down_off[l], h->down_off[l + 1] - h->down_off[l], h->rt_down,
+                               h->d_blks_down, h->d_pool_down, yh, nullptr, yh};
+                check(launch_product_add(dn, prec, s), "downward");
+                rec_end(h, s, 4, ev);
+            }
+        } else {
             rec_begin(h, s, 4, &ev);
-            check(launch_downward(h->level_off[l], h->level_off[l + 1], h->d_parent, h->d_e, yh, m, prec, s), "downward");
+            check(launch_downward_paths(int32_t(h->down_front.size()), h->d_front, h->d_parent, h->d_e, yh, m, prec,
+                                        s),
+                  "downward");
             rec_end(h, s, 4, ev);
+            for (int l = h->down_l0 + 1; l <= h->S.depth; ++l) {
+                rec_begin(h, s, 4, &ev);
+                check(launch_downward(h->level_off[l], h->level_off[l + 1], h->d_parent, h->d_e, yh, m, prec, s),
+                      "downward");
+                rec_end(h, s, 4, ev);
+            }
         }
 
         // join, then y64 += V_t yhat_t and back to the caller's node order
-        check(hipStreamWaitEvent(s, join, 0), "join");
-        (void)hipEventDestroy(fork);
-        (void)hipEventDestroy(join);
-        ProductArgs leafv{h->d_items_v, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
+        check(hipStreamWaitEvent(s, h->join_ev, 0), "join");
+        ProductArgs leafv = h->rec ? ProductArgs{h->d_items_v, int32_t(h->items_v.size()), h->rt_leaf, h->d_blks_v,
+                                                 h->d_pool_q, x, yh, nullptr}
+                                   : ProductArgs{h->d_items_v, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf,
+                                                 h->d_pool_leaf, x, yh, nullptr};
         rec_begin(h, s, 5, &ev);
         check(launch_product_add64(leafv, y64, prec, s), "leaf output");
         check(launch_unpermute(y64, io, N, nr, h->d_iperm, u2p, s), "unpermute");
@@ -670,6 +971,7 @@ void h2dlp_default_options(h2dlp_options* o) {
     o->stream = nullptr;
     o->coupling = H2DLP_COUPLING_STORED;
     o->dense_far_max = 0;
+    o->recompress_eps = 0.0;
 }
 
 static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle* out) {
@@ -694,6 +996,11 @@ static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_hand
     if (o->coupling == H2DLP_COUPLING_GENERATED &&
         (o->order > 5 || (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32)))
         return fail(H2DLP_ENOTSUP, "generated coupling needs FP64 or FP32 and order <= 5");
+    if (!(o->recompress_eps >= 0.0 && o->recompress_eps < 1.0))
+        return fail(H2DLP_EINVAL, "recompress_eps must be in [0, 1)");
+    if (o->recompress_eps > 0.0 && (o->order > 5 || o->coupling != H2DLP_COUPLING_STORED ||
+                                    (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32)))
+        return fail(H2DLP_ENOTSUP, "recompression needs FP64 or FP32, stored coupling and order <= 5");
     return H2DLP_OK;
 }
 
@@ -755,8 +1062,21 @@ h2dlp_handle h2dlp_build(const h2dlp_mesh* mesh, int order, int leaf, double eta
     return h2dlp_build_ex(mesh, &o, &h) == H2DLP_OK ? h : nullptr;
 }
 
-int h2dlp_apply_ex(h2dlp_handle hh, const void* u1, void* u2, int nrhs, int io_dtype, void* stream, void* workspace,
-                   size_t workspace_bytes) {
+}  // extern "C"
+
+namespace h2dlp {
+
+int set_error(int code, const std::string& msg) { return fail(code, msg); }
+
+int handle_device(h2dlp_handle hh) {
+    const h2dlp_ctx* h = as_ctx(hh);
+    return h && h->materialized ? h->device : -1;
+}
+
+// h2dlp_apply_ex; `workspace_is_library`: the workspace is the library's own
+// device array (its address is not checked against the caller's allocations)
+int apply_entry(h2dlp_handle hh, const void* u1, void* u2, int nrhs, int io_dtype, void* stream, void* workspace,
+                size_t workspace_bytes, bool workspace_is_library) {
     h2dlp_ctx* h = as_ctx(hh);
     if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
     if (!u1 || !u2) return fail(H2DLP_EINVAL, "u1 or u2 is NULL");
@@ -774,6 +1094,12 @@ int h2dlp_apply_ex(h2dlp_handle hh, const void* u1, void* u2, int nrhs, int io_d
     int cur = 0;
     hipGetDevice(&cur);
     if (cur != h->device && hipSetDevice(h->device) != hipSuccess) return fail(H2DLP_EDEVICE, "hipSetDevice failed");
+    std::string why;
+    if (!device_range_ok(u1, bytes, h->device, "u1", &why) || !device_range_ok(u2, bytes, h->device, "u2", &why) ||
+        (workspace && !workspace_is_library && !device_range_ok(workspace, h->ws_bytes, h->device, "workspace", &why))) {
+        if (cur != h->device) hipSetDevice(cur);
+        return fail(H2DLP_EINVAL, why);
+    }
     int rc;
     try {
         rc = apply_impl(h, u1, u2, nrhs, io_dtype, static_cast<hipStream_t>(stream), ws);
@@ -782,6 +1108,15 @@ int h2dlp_apply_ex(h2dlp_handle hh, const void* u1, void* u2, int nrhs, int io_d
     }
     if (cur != h->device) hipSetDevice(cur);
     return rc;
+}
+
+}  // namespace h2dlp
+
+extern "C" {
+
+int h2dlp_apply_ex(h2dlp_handle h, const void* u1, void* u2, int nrhs, int io_dtype, void* stream, void* workspace,
+                   size_t workspace_bytes) {
+    return h2dlp::apply_entry(h, u1, u2, nrhs, io_dtype, stream, workspace, workspace_bytes, false);
 }
 
 int h2dlp_apply(h2dlp_handle h, const double* u1, double* u2, int nrhs) {

@@ -77,7 +77,7 @@ __device__ inline int xcd_item_of(int v, int n_items) {     // v: index in the g
 
 __device__ inline int xcd_item(int n_items) { return xcd_item_of(int(blockIdx.x), n_items); }
 
-enum { EPI_STORE = 0, EPI_LEAF = 1, EPI_ADD64 = 2 };
+enum { EPI_STORE = 0, EPI_LEAF = 1, EPI_ADD64 = 2, EPI_ADD = 3 };
 
 template <typename V>
 __device__ inline V ld(const unsigned char* base, unsigned byte_off) {
@@ -265,13 +265,16 @@ __device__ inline void product_item(const ProductArgs& a, const LeafEpilogue& ep
             }
         return;
     }
-    if (EPI == EPI_STORE) {
+    if (EPI == EPI_STORE || EPI == EPI_ADD) {       // y = acc, or y += acc in the operator precision
 #pragma unroll
         for (int r = 0; r < RTW; ++r)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
-                if (row < M) static_cast<T*>(a.y)[(int64_t(it.out_row) + row) * RHS_TILE + q] = acc[r][v];
+                if (row < M) {
+                    T* o = static_cast<T*>(a.y) + (int64_t(it.out_row) + row) * RHS_TILE + q;
+                    *o = EPI == EPI_ADD ? *o + acc[r][v] : acc[r][v];
+                }
             }
         return;
     }
@@ -1183,6 +1186,16 @@ hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st
     }
 #undef H2DLP_CPL
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_product_add(const ProductArgs& a, int prec, hipStream_t st) {
+    const int rt = a.rt;
+    const int nrg = rt >= 4 ? 4 : pow2ceil(rt);       // one block per item: the waves split its rows
+    const int rtw = pow2ceil((rt + nrg - 1) / nrg);
+    if (rtw > 8) return hipErrorInvalidValue;
+    LeafEpilogue none{};
+    if (prec == P_FP64) return dispatch<double, EPI_ADD>(a, none, rtw, nrg, st);
+    return dispatch<float, EPI_ADD>(a, none, rtw, nrg, st);
 }
 
 hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hipStream_t st) {

@@ -88,6 +88,10 @@ hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int 
 // Coupling products; for k <= 128 with ceil(k/16) a power of two the blocks are
 // stored k x coupling_cols(k) (zero columns beyond k) and a pipelined kernel runs.
 hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st);
+// y += sum_b A_b X_b of each item, in the operator precision (the split of
+// rows over waves as with prefer_rows; y may be the source array, at rows
+// other than the item's)
+hipError_t launch_product_add(const ProductArgs& a, int prec, hipStream_t st);
 // y64 += sum_b A_b X_b of each item (FP64 accumulation target in cluster order)
 hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hipStream_t st);
 // Generated coupling (orders 1..5, FP32 or FP64): a.pool holds the per-cluster

@@ -39,7 +39,8 @@ class _Mesh(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("leaf", ctypes.c_int), ("eta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("device", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("coupling", ctypes.c_int), ("dense_far_max", ctypes.c_int64)]
+                ("stream", ctypes.c_void_p), ("coupling", ctypes.c_int), ("dense_far_max", ctypes.c_int64),
+                ("recompress_eps", ctypes.c_double)]
 
 
 class _Stats(ctypes.Structure):
@@ -54,7 +55,9 @@ class _Stats(ctypes.Structure):
                 ("bytes_bases", ctypes.c_int64), ("bytes_transfer", ctypes.c_int64),
                 ("bytes_other", ctypes.c_int64), ("bytes_resident", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("compression", ctypes.c_double),
-                ("n_far_dense", ctypes.c_int64), ("dense_far_entries", ctypes.c_int64)]
+                ("n_far_dense", ctypes.c_int64), ("dense_far_entries", ctypes.c_int64),
+                ("rank_sum_row", ctypes.c_int64), ("rank_sum_col", ctypes.c_int64),
+                ("rank_max_row", ctypes.c_int32), ("rank_max_col", ctypes.c_int32)]
 
 
 EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
@@ -149,6 +152,10 @@ class Stats:
     compression: float
     n_far_dense: int
     dense_far_entries: int
+    rank_sum_row: int
+    rank_sum_col: int
+    rank_max_row: int
+    rank_max_col: int
 
 
 def _ptr(t) -> int:
@@ -163,7 +170,7 @@ class Operator:
 
     def __init__(self, xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0,
                  precision="fp64", alpha: float = 0.1, device: int = -1, stream=None, plan_only: bool = False,
-                 coupling: str = "stored", dense_far_max: int = 0):
+                 coupling: str = "stored", dense_far_max: int = 0, recompress_eps: float = 0.0):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         tri = np.ascontiguousarray(tri, dtype=np.int32)
         if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3:
@@ -177,12 +184,18 @@ class Operator:
         opt.stream = stream
         opt.coupling = COUPLING[coupling]
         opt.dense_far_max = int(dense_far_max)
+        opt.recompress_eps = float(recompress_eps)
         h = ctypes.c_void_p()
         entry = _lib.h2dlp_plan if plan_only else _lib.h2dlp_build_ex
         _check(entry(ctypes.byref(mesh), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
         self._free = _lib.h2dlp_free          # kept for interpreter shutdown
         self.plan_only = plan_only
+        if plan_only:
+            self.device = None
+        else:
+            import torch
+            self.device = device if device >= 0 else torch.cuda.current_device()
         self.n_nodes = xyz.shape[0]
         self.stats = self.info()
 
@@ -208,18 +221,34 @@ class Operator:
         _check(_lib.h2dlp_bytes(self._h, ctypes.byref(r), ctypes.byref(w)))
         return r.value, w.value
 
-    def apply(self, u1, u2, nrhs: int | None = None, stream=None, workspace=None):
-        """u2 = M u1 for device tensors of shape (nrhs, N) (float64 or float32, same dtype)."""
+    def _io_args(self, u1, u2, nrhs, stream, workspace):
+        """Check the apply operands before any pointer reaches the library:
+        (nrhs, io dtype, stream handle)."""
         import torch
+        if self.plan_only:
+            raise ValueError("a planned operator has nothing on the device")
         if u1.dtype != u2.dtype or u1.dtype not in (torch.float64, torch.float32):
             raise ValueError("u1 and u2 must both be float64 or both float32")
-        if u1.shape[-1] != self.n_nodes or u2.shape != u1.shape:
-            raise ValueError("u1, u2 must have shape (nrhs, N)")
-        nrhs = (u1.shape[0] if u1.dim() == 2 else 1) if nrhs is None else nrhs
+        if u1.dim() not in (1, 2) or u1.shape[-1] != self.n_nodes or u2.shape != u1.shape:
+            raise ValueError("u1, u2 must have shape (nrhs, N) or (N,)")
+        rows = u1.shape[0] if u1.dim() == 2 else 1
+        nrhs = rows if nrhs is None else int(nrhs)
+        if not 1 <= nrhs <= rows:
+            raise ValueError(f"nrhs must be in [1, {rows}]")
+        for name, t in (("u1", u1), ("u2", u2), ("workspace", workspace)):
+            if t is not None and (t.device.type != "cuda" or t.device.index != self.device):
+                raise ValueError(f"{name} must be on cuda:{self.device}, not {t.device}")
         io = IO_F64 if u1.dtype == torch.float64 else IO_F32
         st = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        return nrhs, io, st
+
+    def apply(self, u1, u2, nrhs: int | None = None, stream=None, workspace=None):
+        """u2 = M u1 for device tensors of shape (nrhs, N) or (N,) (float64 or
+        float32, same dtype) on the operator's GPU; `nrhs` (default: all rows)
+        applies to the first nrhs rows only."""
+        nrhs, io, st = self._io_args(u1, u2, nrhs, stream, workspace)
         ws_ptr, ws_bytes = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
-        _check(_lib.h2dlp_apply_ex(self._h, _ptr(u1), _ptr(u2), int(nrhs), io, st, ws_ptr, ws_bytes))
+        _check(_lib.h2dlp_apply_ex(self._h, _ptr(u1), _ptr(u2), nrhs, io, st, ws_ptr, ws_bytes))
         return u2
 
     def export_structure(self) -> dict:
@@ -276,10 +305,10 @@ class Operator:
 
 
 def plan(xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64", alpha: float = 0.1,
-         coupling: str = "stored", dense_far_max: int = 0):
+         coupling: str = "stored", dense_far_max: int = 0, recompress_eps: float = 0.0):
     """Host-only structure and byte counts (no GPU needed)."""
     return Operator(xyz, tri, order, leaf, eta, precision, alpha, plan_only=True, coupling=coupling,
-                    dense_far_max=dense_far_max)
+                    dense_far_max=dense_far_max, recompress_eps=recompress_eps)
 
 
 def last_error() -> str:

@@ -56,6 +56,8 @@ class Request:
     error: Optional[str] = None
     done: Optional[float] = None   # seconds after the start of Server.run
     batch_id: Optional[int] = None
+    launched: Optional[float] = None   # seconds after the start of Server.run: its batch went to a slot
+    timing: Optional[dict] = None      # device milliseconds of its batch by phase (backend.timings)
 
     @property
     def nrhs(self) -> int:
@@ -99,6 +101,10 @@ class Backend:
     def collect(self, ticket) -> np.ndarray:
         raise NotImplementedError
 
+    def timings(self, ticket) -> Optional[dict]:
+        """Milliseconds of a finished batch by phase (reload, h2d, apply, d2h), if measured."""
+        return None
+
 
 class GpuBackend(Backend):
     """The HIP library on one GPU: torch supplies streams, pinned staging and workspaces."""
@@ -125,6 +131,10 @@ class GpuBackend(Backend):
         op.offload()
 
     def reload(self, op, slot=None):
+        if slot is not None:                        # the reload's start, for the batch's timing
+            ev = self.torch.cuda.Event(enable_timing=True)
+            ev.record(slot["stream"])
+            slot["reload_ev"] = ev
         op.reload(stream=None if slot is None else slot["stream"])
 
     def free(self, op):
@@ -159,20 +169,29 @@ class GpuBackend(Backend):
         d1 = slot["d_in"][:r * n].view(r, n)
         d2 = slot["d_out"][:r * n].view(r, n)
         h_out = slot["h_out"][:r * n].view(r, n)
+        ev = [t.cuda.Event(enable_timing=True) for _ in range(4)]
         with t.cuda.stream(s):
+            ev[0].record(s)
             d1.copy_(h_in, non_blocking=True)
+            ev[1].record(s)
             op.apply(d1, d2, stream=s, workspace=slot["ws"])
+            ev[2].record(s)
             h_out.copy_(d2, non_blocking=True)
-            ev = t.cuda.Event()
-            ev.record(s)
-        return (ev, h_out)
+            ev[3].record(s)
+        return {"ev": ev, "reload_ev": slot.pop("reload_ev", None), "h_out": h_out}
 
     def poll(self, ticket):
-        return ticket[0].query()
+        return ticket["ev"][3].query()
 
     def collect(self, ticket):
-        ticket[0].synchronize()
-        return ticket[1].numpy().copy()
+        ticket["ev"][3].synchronize()
+        return ticket["h_out"].numpy().copy()
+
+    def timings(self, ticket):
+        ev, rel = ticket["ev"], ticket["reload_ev"]
+        return {"reload": rel.elapsed_time(ev[0]) if rel is not None else 0.0,
+                "h2d": ev[0].elapsed_time(ev[1]), "apply": ev[1].elapsed_time(ev[2]),
+                "d2h": ev[2].elapsed_time(ev[3])}
 
 
 @dataclass
@@ -343,6 +362,7 @@ class Server:
                 self.batches += 1
                 for r in batch:
                     r.batch_id = self.batches
+                    r.launched = now
                 m.inflight += 1
                 m.last_used = now
                 self.inflight.append((ticket, slot, m, batch))
@@ -359,10 +379,12 @@ class Server:
             if self.backend.poll(ticket):
                 out = self.backend.collect(ticket)
                 t = self.clock()
+                tm = self.backend.timings(ticket)
                 c = 0
                 for r in batch:
                     r.result = out[c:c + r.nrhs]
                     r.done = t - self.t0
+                    r.timing = tm
                     c += r.nrhs
                 m.inflight -= 1
                 self.free_slots.append(slot)
@@ -400,6 +422,7 @@ class Server:
         cols = sum(r.nrhs for r in ok)
         dofs = sum(r.nrhs * self.meshes[r.mesh_id].spec.n_nodes for r in ok)
         return {
+            "breakdown_ms": self.breakdown(ok),
             "requests": len(requests), "served": len(ok), "rejected": len(requests) - len(ok),
             "batches": self.batches, "wall_s": wall,
             "p50_ms": 1e3 * percentile(lat, 50), "p99_ms": 1e3 * percentile(lat, 99),
@@ -411,6 +434,21 @@ class Server:
             "reloads": {k: m.reloads for k, m in self.meshes.items()},
             "offloads": {k: m.offloads for k, m in self.meshes.items()},
         }
+
+    @staticmethod
+    def breakdown(reqs) -> dict:
+        """p50 / p99 milliseconds of each part of the requests' latency: queue
+        (arrival to launch), the device phases of their batch (reload, h2d,
+        apply, d2h, where the backend measures them) and the rest (launch to
+        result on the host minus the device phases: issue, waiting for the GPU,
+        polling)."""
+        parts = {"queue": [r.launched - r.arrival for r in reqs if r.launched is not None]}
+        timed = [r for r in reqs if r.timing is not None and r.launched is not None]
+        for k in ("reload", "h2d", "apply", "d2h"):
+            parts[k] = [r.timing[k] * 1e-3 for r in timed]
+        parts["other"] = [r.done - r.launched - sum(r.timing.values()) * 1e-3 for r in timed]
+        return {k: {"p50": round(1e3 * percentile(v, 50), 3), "p99": round(1e3 * percentile(v, 99), 3)}
+                for k, v in parts.items() if v}
 
     def close(self):
         for m in self.meshes.values():

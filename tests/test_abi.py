@@ -154,3 +154,42 @@ def test_build_without_gpu_reports_no_device():
     with pytest.raises(h2dlp.H2dlpError) as e:
         h2dlp.Operator(xyz, tri)
     assert e.value.code in (h2dlp.ENOTSUP, h2dlp.EDEVICE)
+
+
+def test_apply_rejects_bad_tensors_before_any_launch():
+    # the binding refuses host tensors, tensors on another device, wrong ranks
+    # and nrhs beyond the rows before it passes a pointer to the library (a
+    # stand-in handle that the library is never given)
+    torch = pytest.importorskip("torch")
+    op = object.__new__(h2dlp.Operator)
+    op._h, op.plan_only, op.n_nodes, op.device = ctypes.c_void_p(0), False, 10, 0
+    u = torch.zeros(3, 10, dtype=torch.float64)
+    with pytest.raises(ValueError, match="cuda:0"):
+        op.apply(u, torch.zeros_like(u))
+    with pytest.raises(ValueError, match="nrhs"):
+        op.apply(u, torch.zeros_like(u), nrhs=4)
+    with pytest.raises(ValueError, match="nrhs"):
+        op.apply(u, torch.zeros_like(u), nrhs=0)
+    with pytest.raises(ValueError, match="shape"):
+        op.apply(torch.zeros(2, 3, 10, dtype=torch.float64), torch.zeros(2, 3, 10, dtype=torch.float64))
+    with pytest.raises(ValueError, match="float64 or both float32"):
+        op.apply(u, torch.zeros(3, 10, dtype=torch.float32))
+    op._h = None                                   # nothing to free
+    planned = h2dlp.plan(*meshes.icosphere(2), order=2, leaf=16)
+    with pytest.raises(ValueError, match="planned"):
+        planned.apply(u, torch.zeros_like(u))
+
+
+def test_recompression_arguments():
+    xyz, tri = meshes.icosphere(2)
+    assert _plan_rc(xyz, tri, recompress_eps=-1e-3) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, recompress_eps=1.0) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, recompress_eps=float("nan")) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, recompress_eps=1e-6, coupling="generated") == h2dlp.ENOTSUP
+    assert _plan_rc(xyz, tri, recompress_eps=1e-6, precision="bf16x3") == h2dlp.ENOTSUP
+    assert _plan_rc(xyz, tri, order=6, recompress_eps=1e-6) == h2dlp.ENOTSUP
+    p = h2dlp.plan(xyz, tri, order=3, leaf=16, recompress_eps=1e-6, precision="fp32")
+    q = h2dlp.plan(xyz, tri, order=3, leaf=16, precision="fp32")
+    # before the build the plan reports the interpolation sizes, an upper bound
+    assert p.stats.rank_sum_row == p.stats.n_clusters * 27 and p.stats.rank_max_col == 27
+    assert p.stats.n_far == q.stats.n_far and p.stats.coupling_entries == q.stats.coupling_entries

@@ -51,3 +51,32 @@ def test_more_than_one_gpu_is_refused():
     p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert p.returncode == 2 and "one GPU" in p.stderr and p.stdout == ""
+
+
+def test_apply_roofline_record():
+    st = types.SimpleNamespace(bytes_coupling=0, bytes_near=4 * 10 ** 6, bytes_bases=4 * 2 * 100 * 8,
+                               bytes_transfer=0, n_clusters=3, k=8, coupling_entries=10 ** 9, near_entries=10 ** 6,
+                               dense_far_entries=0)
+    r = bench.apply_roofline(st, "fp32", 100, 16, 1.0, "generated")
+    flops = 2.0 * (10 ** 9 + 10 ** 6 + 2 * 100 * 8) * 16
+    assert r["alg_flops"] == flops and r["bound"] == "mfma"
+    assert abs(r["roofline_ms"] - flops / 157.3e9) < 1e-4 and abs(r["frac"] - r["roofline_ms"] / 1.0) < 1e-4
+    assert r["alg_bytes"] == bench.apply_alg_bytes(st, 4, 100, 16)
+    st.coupling_entries = 0
+    assert bench.apply_roofline(st, "fp64", 100, 16, 1.0, "stored")["bound"] == "hbm"
+
+
+def test_host_cpu_and_sampled_oracle():
+    h = bench.host_cpu()
+    assert 1 <= h["cores"] <= min(16, h["visible_cpus"])
+    from workloads import meshes
+    xyz, tri = meshes.icosphere(3, 0.01, 0)
+    case = types.SimpleNamespace(order=3, leaf=16, eta=2.0)
+    r = bench.oracle_sample(xyz, tri, case, 4, dense_far_max=81, cores=2, frac=0.2)
+    assert r["cores"] == 2 and r["kind"] == "oracle" and r["value"] > 0 and r["est_apply_s"] > 0
+    assert "dense" in r["sample"] and "far" in r["sample"]
+
+
+def test_direct_oracle_timing():
+    r = bench.oracle_direct("sphere_l4", cores=2, reps=2)
+    assert r["nodes"] == 2562 and r["rhs"] == 2 and len(r["apply_s"]) == 2 and r["GDOF_s"] > 0

@@ -1,13 +1,30 @@
-"""Full-size GPU checks in the launch configuration the benchmark times.
+"""Full-size GPU checks in the launch configurations the benchmark times.
 
-* Sampled parity: 16 right-hand sides that are unit vectors at seeded nodes.
-  The oracle then needs only the clusters, blocks and bases those nodes touch,
-  yet every output entry (all N rows of each column) is compared.
+* Unit columns at 655362 nodes: 16 right-hand sides that are unit vectors at
+  seeded nodes.  The oracle then needs only the clusters, blocks and bases
+  those nodes touch, yet every output entry (all N rows of each column) is
+  compared.  The output of a unit column is dominated by its diagonal entry
+  D_jj ~ -1/2 (Section 3, eq. matrix_definition), so each check is also made
+  on the double-layer part alone: out - D u against ref - D u, relative to
+  |ref - D u| = |K u|, which is where the far field (Section 4) shows.
+* Sampled rows at 655362 nodes: the benchmarked input itself (16 N(0,1)
+  columns), 1000 seeded rows of the oracle's H2 product for each exact-block
+  threshold, stored by tests/golden/make_l8_rows.py (oracle only).
+* Every precision (FP64, FP32, BF16X3, BF16X6) and both coupling modes, each
+  in the plain interpolation H2 matrix (dense_far_max = 0) and in the
+  configuration the benchmark runs for that mode (admissible blocks with
+  |t||s| <= k^2 exact when stored, <= k^2/2 when generated).
 * Dense rows: at 163842 nodes, 1000 seeded rows of the exact dense matrix
   (Section 3), stored by tests/golden/make_dense_rows.py, bound the H2
   approximation error.
 * Physics at 655362 nodes: u1 = z gives u2 ~ -2z/3 and the sphere's energy
   mu0 Ms^2 V/6 (Section 6.2); M 1 = -1 up to the far-field approximation.
+
+Targets (relative l2 per right-hand side, maximum over the columns): 1e-12
+for FP64 and 1e-6 for FP32, BF16X3 and BF16X6 against the oracle's H2 product;
+1e-4 for the H2 product against the dense matrix.  A case that misses its
+target is reported as an expected failure carrying the measured value, after
+an assertion that bounds it at the level measured so far.
 """
 import os
 
@@ -19,6 +36,25 @@ from workloads import cases, rhs
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN_L7 = os.path.join(HERE, "golden", "sphere_l7_dense_rows.npz")
+GOLDEN_L8 = os.path.join(HERE, "golden", "sphere_l8_h2_rows.npz")
+
+TARGET = {"fp64": 1e-12, "fp32": 1e-6, "bf16x3": 1e-6, "bf16x6": 1e-6}
+# Error relative to |K u| (the double-layer part without the diagonal).
+# Not a target of its own: a rounding error e relative to the full output is
+# e |M u|/|K u| relative to K u, about 15x e for N(0,1) columns on the sphere
+# (|K u| ~ 0.07 |M u|) and 25-50x for unit columns.  FP32 storage of the
+# bases and transfers, rounded again at each of the ~16 levels of the upward
+# and downward passes, gives ~3e-6 of K u; the bounds below are the measured
+# maxima with a factor ~2 of headroom.
+K_BOUND = {"fp64": 1e-11, "fp32": 1e-5, "bf16x3": 1.2e-4, "bf16x6": 1e-5}
+# measured worst cases of the misses below (regression bounds): BF16X3 at
+# 655362 nodes is 4.4e-6 on unit columns and 1.4e-6 on the N(0,1) input with
+# every admissible block low-rank; it meets 1e-6 (9.6e-7) on the N(0,1) input
+# with blocks up to k^2 exact, where fewer products go through bfloat16
+MISS_BOUND = {"bf16x3": 5e-6}
 
 
 @pytest.fixture(scope="module")
@@ -36,9 +72,6 @@ def run(op, u1):
     return d2.cpu().numpy()
 
 
-GOLDEN_ROWS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere_l7_dense_rows.npz")
-
-
 def relerr(a, b):
     return np.linalg.norm(a - b, axis=-1) / np.linalg.norm(b, axis=-1)
 
@@ -50,39 +83,20 @@ def unit_columns(n, count, seed):
     return u
 
 
-@pytest.fixture(scope="module")
-def sphere_l7():
-    c = cases.CASES["sphere_l7"]
-    xyz, tri = cases.mesh_of(c.mesh)
-    H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False)
-    u = unit_columns(xyz.shape[0], 16, 11)
-    return c, xyz, tri, u, H.apply(u)
+def check_target(prec, err, what):
+    """Assert the target; a known miss is bounded, then reported as xfail with its value."""
+    worst = float(np.max(err))
+    if worst <= TARGET[prec]:
+        return
+    assert prec in MISS_BOUND and worst <= MISS_BOUND[prec], f"{what}: {prec} error {worst:.3e}"
+    pytest.xfail(f"{what}: {prec} misses {TARGET[prec]:g} (measured {worst:.2e})")
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
-def test_sphere_l7_sampled_columns(lib, sphere_l7, prec, tol):
-    c, xyz, tri, u, ref = sphere_l7
-    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec)
-    err = relerr(run(op, u), ref)
-    assert np.all(err <= tol), err
+# ------------------------------------------------------------------ 655362 nodes
 
-
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_sphere_l7_dense_rows(lib, sphere_l7, prec):
-    # 1000 exact rows of M u1 (tests/golden/make_dense_rows.py, oracle only)
-    c, xyz, tri, _, _ = sphere_l7
-    g = np.load(GOLDEN_ROWS)
-    rows, ref = g["rows"], g["values"]
-    n = xyz.shape[0]
-    assert int(g["n_nodes"]) == n
-    u = np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(n, 8, 0)])
-    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec)
-    err = relerr(run(op, u)[:, rows], ref)
-    print(f"{prec}: H2 vs 1000 dense rows, per column: {np.array2string(err, precision=2)}")
-    # interpolation error of the H2 approximation at order 4, not arithmetic
-    # (FP32 and FP64 agree to 3e-7): ~2.4e-4 for the smooth u1 = z and ~3e-5
-    # for N(0,1) columns; the paper fixes no bound here
-    assert err[0] <= 5e-4 and np.all(err[1:] <= 1e-4), err
+L8_CONFIGS = [(p, c, d) for p, c in (("fp64", "stored"), ("fp64", "generated"), ("fp32", "stored"),
+                                     ("fp32", "generated"), ("bf16x3", "stored"), ("bf16x6", "stored"))
+              for d in (0, 15625 if c == "stored" else 7812)]
 
 
 @pytest.fixture(scope="module")
@@ -92,14 +106,56 @@ def sphere_l8():
     return c, xyz, tri
 
 
-def test_sphere_l8_sampled_columns_fp32(lib, sphere_l8):
+@pytest.fixture(scope="module")
+def l8_oracle(sphere_l8):
     c, xyz, tri = sphere_l8
     H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False)
     u = unit_columns(xyz.shape[0], 16, 12)
-    ref = H.apply(u)
-    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp32")
-    err = relerr(run(op, u), ref)
-    assert np.all(err <= 1e-6), err
+    refs = {}
+
+    def ref(dmax):
+        if dmax not in refs:
+            refs[dmax] = H.with_dense_far_max(dmax).apply(u)
+        return refs[dmax]
+    return H, u, ref
+
+
+@pytest.fixture(scope="module")
+def l8_rows(sphere_l8):
+    c, xyz, tri = sphere_l8
+    g = np.load(GOLDEN_L8)
+    assert int(g["n_nodes"]) == xyz.shape[0]
+    return g, rhs.normal_rhs(xyz.shape[0], 16, 0)
+
+
+@pytest.mark.parametrize("prec,coupling,dmax", L8_CONFIGS)
+def test_sphere_l8_against_oracle(lib, sphere_l8, l8_oracle, l8_rows, prec, coupling, dmax):
+    c, xyz, tri = sphere_l8
+    H, u, ref_of = l8_oracle
+    g, un = l8_rows
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec, coupling=coupling,
+                      dense_far_max=dmax)
+    assert op.stats.n_far_dense == H.with_dense_far_max(dmax).far_dense.shape[0]
+    d_gpu = op.export_diagonal()
+    # unit columns: all N rows
+    ref = ref_of(dmax)
+    out = run(op, u)
+    k_ref = ref - H.D[None, :] * u
+    e_unit = relerr(out, ref)
+    e_unit_k = relerr(out - d_gpu[None, :] * u, k_ref)
+    # the benchmarked N(0,1) input: 1000 sampled rows
+    rows, ref_rows = g["rows"], g[f"values_{dmax}"]
+    out_rows = run(op, un)[:, rows]
+    k_rows = ref_rows - g["diag"][None, :] * un[:, rows]
+    e_rows = relerr(out_rows, ref_rows)
+    e_rows_k = relerr(out_rows - d_gpu[rows][None, :] * un[:, rows], k_rows)
+    op.close()
+    print(f"L8 {prec} {coupling} dense_far_max={dmax}: unit columns {e_unit.max():.2e} (of K u: "
+          f"{e_unit_k.max():.2e}); N(0,1) rows {e_rows.max():.2e} (of K u: {e_rows_k.max():.2e})")
+    assert np.all(e_unit_k <= K_BOUND[prec]), e_unit_k
+    assert np.all(e_rows_k <= K_BOUND[prec]), e_rows_k
+    check_target(prec, e_rows, f"L8 {coupling} dense_far_max={dmax}, N(0,1) input")
+    check_target(prec, e_unit, f"L8 {coupling} dense_far_max={dmax}, unit columns")
 
 
 def test_sphere_l8_uniform_magnetisation(lib, sphere_l8):
@@ -115,42 +171,6 @@ def test_sphere_l8_uniform_magnetisation(lib, sphere_l8):
     assert np.max(np.abs(out[1] + 1.0)) < 2e-3
 
 
-@pytest.fixture(scope="module")
-def film():
-    c = cases.CASES["film"]
-    xyz, tri = cases.mesh_of(c.mesh)
-    return c, xyz, tri
-
-
-def test_film_sampled_columns_fp64(lib, film):
-    c, xyz, tri = film
-    H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False)
-    u = unit_columns(xyz.shape[0], 16, 13)
-    ref = H.apply(u)
-    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp64")
-    err = relerr(run(op, u), ref)
-    assert np.all(err <= 1e-12), err
-
-
-def test_film_fp32_smooth_fields(lib, film):
-    # FP32 against the FP64 path (itself the oracle's to 1e-12) on the four
-    # smooth fields.  On the flat faces the far field of coplanar clusters is
-    # a sum of large terms that cancel (the normal derivative of the kernel
-    # taken through Chebyshev points across a box only alpha = 0.1 of its
-    # length thick), so FP32 rounding is amplified: measured 4.5e-6, against
-    # 2e-7 on the sphere
-    c, xyz, tri = film
-    u = rhs.smooth_fields(xyz, c.nrhs)
-    outs = {}
-    for prec in ("fp64", "fp32"):
-        op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec)
-        outs[prec] = run(op, u)
-        op.close()
-    err = relerr(outs["fp32"], outs["fp64"])
-    print(f"film fp32 vs fp64: {np.array2string(err, precision=2)}")
-    assert np.all(err <= 1e-5), err
-
-
 def test_unjittered_sphere_l8_energy(lib):
     # the same energy check on the level-8 sphere without jitter: the jittered
     # polyhedron is rough (jitter ~0.3 edge lengths), the smooth one is not
@@ -164,18 +184,96 @@ def test_unjittered_sphere_l8_energy(lib):
     assert abs(e / (vol / 6.0) - 1.0) < 1e-3
 
 
-def test_sphere_l8_bench_configuration(lib, sphere_l8):
-    # the configuration bench.py times: generated coupling, admissible blocks
-    # with |t||s| <= k^2/2 kept exact, FP32; sampled unit columns against the
-    # oracle built with the same block choice
-    c, xyz, tri = sphere_l8
-    dmax = (c.order ** 3) ** 2 // 2
-    H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False, dense_far_max=dmax)
-    u = unit_columns(xyz.shape[0], 16, 14)
-    ref = H.apply(u)
-    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp32", coupling="generated",
+# ------------------------------------------------------------------ 163842 nodes
+
+@pytest.fixture(scope="module")
+def sphere_l7():
+    c = cases.CASES["sphere_l7"]
+    xyz, tri = cases.mesh_of(c.mesh)
+    H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False)
+    u = unit_columns(xyz.shape[0], 16, 11)
+    return c, xyz, tri, H, u, H.apply(u)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sphere_l7_unit_columns(lib, sphere_l7, prec):
+    c, xyz, tri, H, u, ref = sphere_l7
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec)
+    out = run(op, u)
+    err = relerr(out, ref)
+    err_k = relerr(out - op.export_diagonal()[None, :] * u, ref - H.D[None, :] * u)
+    print(f"L7 {prec}: unit columns {err.max():.2e} (of K u: {err_k.max():.2e})")
+    assert np.all(err_k <= K_BOUND[prec]), err_k
+    check_target(prec, err, "L7 unit columns")
+
+
+@pytest.mark.parametrize("prec,coupling,dmax", [("fp64", "stored", 0), ("fp32", "stored", 0),
+                                                ("fp64", "generated", 2048), ("fp32", "generated", 2048),
+                                                ("fp32", "stored", 4096)])
+def test_sphere_l7_dense_rows(lib, sphere_l7, prec, coupling, dmax):
+    # 1000 exact rows of M u1 (tests/golden/make_dense_rows.py, oracle only):
+    # the H2 approximation error at order 4, in the plain H2 matrix and with
+    # small admissible blocks exact (dense_far_max = k^2/2 generated, k^2 stored)
+    c, xyz, tri, _, _, _ = sphere_l7
+    g = np.load(GOLDEN_L7)
+    rows, ref = g["rows"], g["values"]
+    n = xyz.shape[0]
+    assert int(g["n_nodes"]) == n
+    u = np.vstack([rhs.z_rhs(xyz), rhs.normal_rhs(n, 8, 0)])
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec, coupling=coupling,
                       dense_far_max=dmax)
-    assert op.stats.n_far_dense == H.counts()["far_dense"]
-    err = relerr(run(op, u), ref)
-    print(f"bench configuration vs oracle: {np.array2string(err, precision=2)}")
-    assert np.all(err <= 1e-6), err
+    err = relerr(run(op, u)[:, rows], ref)
+    print(f"L7 {prec} {coupling} dense_far_max={dmax}: H2 vs 1000 dense rows, per column: "
+          f"{np.array2string(err, precision=2)}")
+    assert np.all(err[1:] <= 1e-4), err
+    if err[0] > 1e-4:
+        # u1 = z at order 4: measured 2.28e-4 to 2.32e-4 whatever the exact
+        # small blocks, so the error sits in the larger admissible blocks
+        assert err[0] <= 3e-4, err
+        pytest.xfail(f"H2 vs dense 1e-4 missed at order 4 for u1 = z ({err[0]:.2e})")
+
+
+# ------------------------------------------------------------------ thin film
+
+@pytest.fixture(scope="module")
+def film():
+    c = cases.CASES["film"]
+    xyz, tri = cases.mesh_of(c.mesh)
+    return c, xyz, tri
+
+
+def test_film_unit_columns_fp64(lib, film):
+    c, xyz, tri = film
+    H = h2.H2Oracle(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, cache_coupling=False)
+    u = unit_columns(xyz.shape[0], 16, 13)
+    ref = H.apply(u)
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp64")
+    out = run(op, u)
+    err = relerr(out, ref)
+    err_k = relerr(out - op.export_diagonal()[None, :] * u, ref - H.D[None, :] * u)
+    print(f"film fp64: unit columns {err.max():.2e} (of K u: {err_k.max():.2e})")
+    assert np.all(err <= 1e-12) and np.all(err_k <= K_BOUND["fp64"]), (err, err_k)
+
+
+@pytest.mark.parametrize("coupling,dmax", [("stored", 0), ("generated", 7812), ("stored", 15625)])
+def test_film_fp32_smooth_fields(lib, film, coupling, dmax):
+    # FP32 against the FP64 path of the same operator (itself the oracle's to
+    # 1e-12) on the four smooth fields.  On the flat faces the far field of
+    # coplanar clusters is a sum of large terms that cancel (the normal
+    # derivative of the kernel taken through Chebyshev points across a box
+    # only alpha = 0.1 of its length thick), so FP32 rounding is amplified
+    c, xyz, tri = film
+    u = rhs.smooth_fields(xyz, c.nrhs)
+    outs = {}
+    for prec in ("fp64", "fp32"):
+        op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec, coupling=coupling,
+                          dense_far_max=dmax)
+        outs[prec] = run(op, u)
+        op.close()
+    err = relerr(outs["fp32"], outs["fp64"])
+    print(f"film fp32 {coupling} dense_far_max={dmax} vs fp64: {np.array2string(err, precision=2)}")
+    if np.max(err) > 1e-6:
+        # measured 4.5e-6 with or without the exact small blocks: the
+        # amplified rounding sits in the larger coplanar admissible blocks
+        assert np.max(err) <= 6e-6, err
+        pytest.xfail(f"film FP32 misses 1e-6 (measured {np.max(err):.2e})")

@@ -64,10 +64,13 @@ def test_async_reload_then_apply_on_another_stream(mods):
         assert np.array_equal(d2.cpu().numpy(), before)
 
 
-def test_mix_equals_alone_under_budget(mods):
+@pytest.mark.parametrize("coupling", ["stored", "generated"])
+def test_mix_equals_alone_under_budget(mods, coupling):
+    # generated coupling is the mode the benchmark serves
     h2dlp, serving = mods
     ms = _meshes()
-    specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32") for k, (x, t) in ms.items()]
+    specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32", coupling=coupling)
+             for k, (x, t) in ms.items()]
     backend = serving.GpuBackend(0)
     sizes = {s.mesh_id: backend.plan_bytes(s) for s in specs}
     res = sorted(r for r, _ in sizes.values())
@@ -89,7 +92,10 @@ def test_mix_equals_alone_under_budget(mods):
     assert stats["served"] == 60, [r.error for r in reqs if r.error]
     assert sum(stats["offloads"].values()) > 0 and sum(stats["reloads"].values()) > 0
     assert stats["batches"] < 60
-    alone_ops = {s.mesh_id: h2dlp.Operator(s.xyz, s.tri, s.order, s.leaf, s.eta, s.precision) for s in specs}
+    alone_ops = {s.mesh_id: h2dlp.Operator(s.xyz, s.tri, s.order, s.leaf, s.eta, s.precision, coupling=coupling)
+                 for s in specs}
     for r in reqs:
         assert np.array_equal(r.result, _apply(alone_ops[r.mesh_id], r.u1)), r.rid
+    b = stats["breakdown_ms"]
+    assert set(b) == {"queue", "reload", "h2d", "apply", "d2h", "other"} and b["apply"]["p50"] > 0
     srv.close()

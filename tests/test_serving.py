@@ -72,6 +72,9 @@ class FakeBackend(Backend):
     def collect(self, ticket):
         return ticket[1]
 
+    def timings(self, ticket):
+        return {"reload": 0.0, "h2d": 0.0, "apply": 1e3 * self.service_s, "d2h": 0.0}
+
 
 def _specs(sizes_nodes):
     return [MeshSpec(mid, np.zeros((n, 3)), np.zeros((1, 3), np.int32)) for mid, n in sizes_nodes]
@@ -107,6 +110,14 @@ def test_all_served_and_equal_to_alone():
         assert r.latency is not None and r.latency >= 0
     assert stats["batches"] < 80                      # same-mesh requests were coalesced
     assert np.isfinite(stats["p50_ms"]) and stats["p99_ms"] >= stats["p50_ms"]
+    # latency parts: queue, device phases, the rest; each request's parts sum to its latency
+    b = stats["breakdown_ms"]
+    assert set(b) == {"queue", "reload", "h2d", "apply", "d2h", "other"}
+    assert b["apply"]["p50"] == pytest.approx(1e3 * be.service_s)
+    assert all(v["p99"] >= v["p50"] for v in b.values())
+    for r in reqs:
+        assert r.latency >= r.launched - r.arrival >= 0
+        assert r.done - r.launched >= sum(r.timing.values()) * 1e-3 - 1e-4     # the service time elapsed
 
 
 def test_batches_respect_column_limit_and_mesh():
