@@ -168,6 +168,22 @@ int h2dlp_apply(h2dlp_handle h, const double* u1, double* u2, int nrhs);
 int h2dlp_apply_ex(h2dlp_handle h, const void* u1, void* u2, int nrhs, int io_dtype,
                    void* stream, void* workspace, size_t workspace_bytes);
 
+/* Allocation-free apply, for callers that cannot allocate device memory: code
+ * under HIP graph capture, fixed serving loops, harnesses that forbid
+ * hipMalloc.  As h2dlp_apply_ex, with the workspace in a device array of the
+ * library instead of the handle's or the caller's: H2DLP_NOALLOC_SCRATCH_BYTES
+ * (128 MiB) per GPU, held from the load of the library until the process
+ * ends.  The call allocates nothing (no hipMalloc, hipFree, stream or event
+ * creation); its first use on a device looks up the array's address there.
+ * All calls on one GPU share that GPU's array and it keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one
+ * GPU -- other streams, threads or handles -- race, so the caller runs them one
+ * after another.  Profiling (h2dlp_profile) creates events: keep it off here.
+ * Errors: as h2dlp_apply_ex; ENOMEM when h2dlp_stats.workspace_bytes exceeds
+ * H2DLP_NOALLOC_SCRATCH_BYTES (use h2dlp_apply_ex with a workspace then). */
+#define H2DLP_NOALLOC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int h2dlp_apply_noalloc(h2dlp_handle h, const void* u1, void* u2, int nrhs, int io_dtype, void* stream);
+
 /* Device bytes held by the handle and needed per concurrent apply (admission by HBM budget). */
 int h2dlp_bytes(h2dlp_handle h, size_t* resident, size_t* workspace);
 

@@ -48,7 +48,8 @@ def build(verbose: bool = False) -> str:
                            ("api.cpp", ["-x", "c++"]),
                            ("build_kernels.hip", []),
                            ("apply_kernels.hip", []),
-                           ("recompress.hip", [])):
+                           ("recompress.hip", []),
+                           ("noalloc.hip", [])):
             obj = os.path.join(tmp, src + ".o")
             cmd = [hipcc, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
             if src.endswith(".cpp"):

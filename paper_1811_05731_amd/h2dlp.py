@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "libh2dlp.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOTSUP = 0, -1, -2, -3, -4
 FP64, FP32, BF16X3, BF16X6 = 0, 1, 2, 3
 IO_F64, IO_F32 = 0, 1
+NOALLOC_SCRATCH_BYTES = 128 * 1024 * 1024      # H2DLP_NOALLOC_SCRATCH_BYTES
 NKINDS = 7
 KIND_NAMES = ("permute", "leaf_forward", "upward", "coupling", "downward", "leaf_output", "near_field")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
@@ -62,7 +63,7 @@ class _Stats(ctypes.Structure):
 
 EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
             "h2dlp_bytes", "h2dlp_info", "h2dlp_export_structure", "h2dlp_export_diagonal", "h2dlp_offload",
-            "h2dlp_reload", "h2dlp_reload_ex", "h2dlp_free",
+            "h2dlp_reload", "h2dlp_reload_ex", "h2dlp_free", "h2dlp_apply_noalloc",
             "h2dlp_last_error", "h2dlp_profile", "h2dlp_profile_read")
 
 
@@ -87,6 +88,8 @@ def _load():
     lib.h2dlp_apply.restype = I
     lib.h2dlp_apply_ex.argtypes = [V, V, V, I, I, V, V, ctypes.c_size_t]
     lib.h2dlp_apply_ex.restype = I
+    lib.h2dlp_apply_noalloc.argtypes = [V, V, V, I, I, V]
+    lib.h2dlp_apply_noalloc.restype = I
     lib.h2dlp_bytes.argtypes = [V, P(ctypes.c_size_t), P(ctypes.c_size_t)]
     lib.h2dlp_bytes.restype = I
     lib.h2dlp_info.argtypes = [V, P(_Stats)]
@@ -249,6 +252,14 @@ class Operator:
         nrhs, io, st = self._io_args(u1, u2, nrhs, stream, workspace)
         ws_ptr, ws_bytes = (None, 0) if workspace is None else (_ptr(workspace), workspace.numel() * workspace.element_size())
         _check(_lib.h2dlp_apply_ex(self._h, _ptr(u1), _ptr(u2), nrhs, io, st, ws_ptr, ws_bytes))
+        return u2
+
+    def apply_noalloc(self, u1, u2, nrhs: int | None = None, stream=None):
+        """As apply(), with the workspace in the library's own device array
+        (h2dlp_apply_noalloc): nothing is allocated, and calls on one GPU must
+        not overlap."""
+        nrhs, io, st = self._io_args(u1, u2, nrhs, stream, None)
+        _check(_lib.h2dlp_apply_noalloc(self._h, _ptr(u1), _ptr(u2), nrhs, io, st))
         return u2
 
     def export_structure(self) -> dict:
