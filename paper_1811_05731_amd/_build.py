@@ -66,7 +66,7 @@ def build(verbose: bool = False) -> str:
                 print(out)
         tmp_lib = LIB + ".tmp"
         _run([hipcc, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp_lib, *objs,
-              "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
+              "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"])
         os.replace(tmp_lib, LIB)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)

@@ -158,6 +158,36 @@ def test_sphere_l8_against_oracle(lib, sphere_l8, l8_oracle, l8_rows, prec, coup
     check_target(prec, e_unit, f"L8 {coupling} dense_far_max={dmax}, unit columns")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_sphere_l8_recompressed(lib, sphere_l8, l8_oracle, l8_rows, prec):
+    # the recompressed operator (tolerance 1e-6) against the oracle's
+    # interpolation matrix it approximates: the recompression's own error
+    # (<= 10 eps of |K u| by the oracle's pins) plus rounding, on unit columns
+    # and on the benchmarked input
+    c, xyz, tri = sphere_l8
+    H, u, ref_of = l8_oracle
+    g, un = l8_rows
+    eps = 1e-6
+    op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec, recompress_eps=eps)
+    st = op.stats
+    assert st.rank_max_row <= st.k and st.rank_sum_row < st.n_clusters * st.k
+    d_gpu = op.export_diagonal()
+    ref = ref_of(0)
+    out = run(op, u)
+    e_unit = relerr(out, ref)
+    e_unit_k = relerr(out - d_gpu[None, :] * u, ref - H.D[None, :] * u)
+    rows, ref_rows = g["rows"], g["values_0"]
+    out_rows = run(op, un)[:, rows]
+    e_rows = relerr(out_rows, ref_rows)
+    e_rows_k = relerr(out_rows - d_gpu[rows][None, :] * un[:, rows], ref_rows - g["diag"][None, :] * un[:, rows])
+    op.close()
+    print(f"L8 recompressed {prec}: ranks {st.rank_sum_row / st.n_clusters:.1f}/{st.rank_sum_col / st.n_clusters:.1f} "
+          f"coupling {st.coupling_entries}; unit columns {e_unit.max():.2e} (of K u: {e_unit_k.max():.2e}); "
+          f"N(0,1) rows {e_rows.max():.2e} (of K u: {e_rows_k.max():.2e})")
+    assert np.all(e_unit <= 1e-6) and np.all(e_rows <= 1e-6), (e_unit, e_rows)
+    assert np.all(e_unit_k <= 10 * eps) and np.all(e_rows_k <= 10 * eps), (e_unit_k, e_rows_k)
+
+
 def test_sphere_l8_uniform_magnetisation(lib, sphere_l8):
     c, xyz, tri = sphere_l8
     op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp32")
