@@ -151,8 +151,8 @@ struct h2dlp_ctx {
     // the near field runs on this stream while the far-field chain runs on the caller's;
     // fork and join order it against the caller's stream (created once: an apply
     // creates no event)
-    hipStream_t side = nullptr;
-    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+    hipStream_t side = nullptr, side2 = nullptr;
+    hipEvent_t fork_ev = nullptr, mid_ev = nullptr, join_ev = nullptr, cut_ev = nullptr, upper_ev = nullptr;
     // a reload enqueued on a stream: every later use of the device buffers waits for it
     hipEvent_t ready = nullptr;
     bool ready_pending = false;
@@ -190,6 +190,12 @@ struct h2dlp_ctx {
     BlkDesc* d_blks_v = nullptr;
     std::vector<int32_t> up_off, up_end, down_off;   // item ranges by level: [up_off[l], up_end[l]),
                                                      // [down_off[l], down_off[l + 1])
+    // the coupling in two launches: blocks whose source cluster is at level
+    // up_cut or deeper (d_items_cpl, storing y^) run while the upward pass
+    // finishes levels above up_cut on side2; the rest (d_items_cpl_b) add
+    ItemDesc* d_items_cpl_b = nullptr;
+    int32_t n_items_cpl_b = 0;
+    int up_cut = 0;
     int32_t rt_fwd = 1, rt_up = 1, rt_cpl = 1, rt_down = 1;
     h2dlp_stats st{};
     // profiling
@@ -207,7 +213,11 @@ struct h2dlp_ctx {
         for (auto& r : recs) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
         if (ready) { (void)hipEventSynchronize(ready); (void)hipEventDestroy(ready); }
         if (side) { (void)hipStreamSynchronize(side); (void)hipStreamDestroy(side); }
+        if (side2) { (void)hipStreamSynchronize(side2); (void)hipStreamDestroy(side2); }
+        if (cut_ev) (void)hipEventDestroy(cut_ev);
+        if (upper_ev) (void)hipEventDestroy(upper_ev);
         if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (mid_ev) (void)hipEventDestroy(mid_ev);
         if (join_ev) (void)hipEventDestroy(join_ev);
         for (auto& b : bufs) if (b.p) (void)hipFree(b.p);
         for (auto& p : parked) if (p.host) (void)hipHostFree(p.host);
@@ -228,6 +238,7 @@ struct h2dlp_ctx {
                 {(void**)&d_ns_val, false}, {(void**)&d_pool_up, false}, {(void**)&d_pool_down, false},
                 {(void**)&d_pool_q, false}, {(void**)&d_items_up, false}, {(void**)&d_blks_up, false},
                 {(void**)&d_items_down, false}, {(void**)&d_blks_down, false}, {(void**)&d_blks_v, false},
+                {(void**)&d_items_cpl_b, false},
                 {(void**)&d_ws, true}};
     }
     size_t bytes_of(void* p) const {
@@ -592,18 +603,51 @@ void recompress_impl(h2dlp_ctx* h, const double* d_boxes, const double* wt64, co
         }
         h->up_end[l] = int32_t(items_up.size());
     }
-    std::vector<int64_t> a_s(h->far_t.size(), 0);
-    for (size_t b = 0, g = 0; g < size_t(C); ++g) {    // y^_t = sum_s S'_ts x^_s
-        const int32_t b0 = int32_t(h->blks_cpl.size());
-        for (; b < h->far_t.size() && h->far_t[b] == int32_t(g); ++b) {
-            const int32_t s = h->far_s[b];
-            if (rr[g] == 0 || rc[s] == 0) continue;
-            o_s = align_block(o_s);
-            a_s[b] = o_s;
-            h->blks_cpl.push_back(BlkDesc{o_s, rc[s], xo[s]});
-            o_s += int64_t(rr[g]) * rc[s];
+    // y^_t = sum_s S'_ts x^_s in two launches split at level up_cut of the
+    // source: the deepest cut that leaves at most 1/8 of the coupling bytes to
+    // the second launch, so that the latency-bound top of the upward pass
+    // runs beside the first
+    std::vector<int32_t> lvl(C, 0);
+    for (int l = 0; l <= S.depth; ++l)
+        for (int32_t g = h->level_off[l]; g < h->level_off[l + 1]; ++g) lvl[g] = l;
+    {
+        std::vector<int64_t> by_level(S.depth + 2, 0);
+        int64_t total = 0;
+        for (size_t b = 0; b < h->far_t.size(); ++b) {
+            const int64_t n = int64_t(rr[h->far_t[b]]) * rc[h->far_s[b]];
+            by_level[lvl[h->far_s[b]]] += n;
+            total += n;
         }
-        if (rr[g] > 0) h->items_cpl.push_back(ItemDesc{yo[g], rr[g], b0, int32_t(h->blks_cpl.size())});
+        h->up_cut = 0;
+        int64_t above = 0;                             // entries with sources above level l
+        for (int l = 0; l <= S.depth; ++l) {
+            if (8 * (above + by_level[l]) > total) break;
+            above += by_level[l];
+            h->up_cut = l + 1;
+        }
+        h->up_cut = std::min(h->up_cut, S.depth);
+    }
+    std::vector<int64_t> a_s(h->far_t.size(), 0);
+    std::vector<ItemDesc> items_cpl_b;
+    for (size_t b = 0, g = 0; g < size_t(C); ++g) {
+        const int32_t b0 = int32_t(h->blks_cpl.size());
+        const size_t bb = b;
+        for (; b < h->far_t.size() && h->far_t[b] == int32_t(g); ++b) {}
+        int32_t nb_a = 0;
+        for (int pass = 0; pass < 2; ++pass)           // sources at up_cut or deeper first
+            for (size_t q = bb; q < b; ++q) {
+                const int32_t s = h->far_s[q];
+                if (rr[g] == 0 || rc[s] == 0 || (lvl[s] >= h->up_cut) != (pass == 0)) continue;
+                o_s = align_block(o_s);
+                a_s[q] = o_s;
+                h->blks_cpl.push_back(BlkDesc{o_s, rc[s], xo[s]});
+                o_s += int64_t(rr[g]) * rc[s];
+                nb_a += pass == 0;
+            }
+        if (rr[g] == 0) continue;
+        const int32_t b1 = int32_t(h->blks_cpl.size());
+        h->items_cpl.push_back(ItemDesc{yo[g], rr[g], b0, b0 + nb_a});
+        if (b0 + nb_a < b1) items_cpl_b.push_back(ItemDesc{yo[g], rr[g], b0 + nb_a, b1});
     }
     h->down_off.assign(S.depth + 2, 0);
     for (int l = 0; l <= S.depth; ++l) {               // y^_c += F_c y^_parent
@@ -652,6 +696,8 @@ void recompress_impl(h2dlp_ctx* h, const double* d_boxes, const double* wt64, co
     h->d_blks_up = h->upload(blks_up, kept, stream);
     h->d_items_cpl = h->upload(h->items_cpl, kept, stream);
     h->d_blks_cpl = h->upload(h->blks_cpl, kept, stream);
+    h->d_items_cpl_b = items_cpl_b.empty() ? nullptr : h->upload(items_cpl_b, kept, stream);
+    h->n_items_cpl_b = int32_t(items_cpl_b.size());
     h->d_items_down = h->upload(items_down, kept, stream);
     h->d_blks_down = h->upload(blks_down, kept, stream);
     h->d_items_v = h->upload(h->items_v, kept, stream);
@@ -717,7 +763,11 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_blks_leaf = h->upload(h->blks_leaf, &kept, stream);
     h->d_items_near = h->upload(h->items_near, &kept, stream);
     check(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "side stream");
+    check(hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking), "side stream");
+    check(hipEventCreateWithFlags(&h->cut_ev, hipEventDisableTiming), "event");
+    check(hipEventCreateWithFlags(&h->upper_ev, hipEventDisableTiming), "event");
     check(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming), "event");
+    check(hipEventCreateWithFlags(&h->mid_ev, hipEventDisableTiming), "event");
     check(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming), "event");
     {
         int dev = 0, lds_cu = 0, lds_wg = 0;
@@ -874,42 +924,75 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         check(launch_permute(u1p, io, N, nr, h->d_iperm, x, h->ws_x64 ? x64 : nullptr, prec, s), "permute");
         rec_end(h, s, 0, ev);
 
+        // on the side stream from here on: y64 = D x64 + the FP64 near-singular
+        // part, then y64 += the near-field blocks (they read only x and x64),
+        // beside the far-field chain on the caller's stream.  With stored
+        // coupling the near field starts at once (both HBM-bound; it fills the
+        // latency-bound upward pass); with generated coupling (MFMA-bound) it
+        // waits for the upward pass, which it would otherwise slow more than
+        // it gains.
+        const bool near_early = h->d_cgeo == nullptr;
+        ProductArgs nearp{h->d_items_near, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, nullptr,
+                          nullptr};
+        check(hipEventRecord(h->fork_ev, s), "event record");
+        check(hipStreamWaitEvent(h->side, h->fork_ev, 0), "fork");
+        rec_begin(h, h->side, 6, &ev);
+        {
+            LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
+            check(launch_diag_nearsing(epi, N, h->side), "diagonal");
+            if (near_early) check(launch_product_near(nearp, y64, prec, h->side), "near field");
+        }
+        rec_end(h, h->side, 6, ev);
+
         ProductArgs fwd{h->d_items_fwd, h->n_items_fwd, h->rec ? h->rt_fwd : (k + 15) / 16, h->d_blks_fwd,
                         h->d_pool_wt, x, nullptr, xh};
         rec_begin(h, s, 1, &ev);
         check(launch_product_store(fwd, prec, true, s), "leaf forward");
         rec_end(h, s, 1, ev);
 
+        // levels above up_cut (recompressed, split coupling) go to side2, beside
+        // the first coupling launch
+        const int cut = h->n_items_cpl_b > 0 ? h->up_cut : 0;
         for (int l = h->S.depth - 1; l >= 0; --l) {
-            rec_begin(h, s, 2, &ev);
+            hipStream_t su = s;
+            if (l == cut - 1) {
+                check(hipEventRecord(h->cut_ev, s), "event record");
+                check(hipStreamWaitEvent(h->side2, h->cut_ev, 0), "fork");
+            }
+            if (l < cut) su = h->side2;
+            rec_begin(h, su, 2, &ev);
             if (h->rec) {      // x^_t = sum_c F'_c^T x^_c, a grouped product per level
                 ProductArgs up{h->d_items_up + h->up_off[l], h->up_end[l] - h->up_off[l], h->rt_up, h->d_blks_up,
                                h->d_pool_up, xh, nullptr, xh};
-                check(launch_product_store(up, prec, true, s), "upward");
+                check(launch_product_store(up, prec, true, su), "upward");
             } else {
                 check(launch_upward(h->level_off[l], h->level_off[l + 1], h->d_child0, h->d_child1, h->d_e, xh, m,
-                                    prec, s),
+                                    prec, su),
                       "upward");
             }
-            rec_end(h, s, 2, ev);
+            rec_end(h, su, 2, ev);
         }
+        if (cut > 0) check(hipEventRecord(h->upper_ev, h->side2), "event record");
 
-        ProductArgs nearp{h->d_items_near, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, yh, nullptr};
-        LeafEpilogue epi{h->d_diag, x64, y64, h->d_ns_off, h->d_ns_pos, h->d_ns_val};
-        // near field, diagonal and near-singular part into y64 on the side stream,
-        // beside the coupling products (HBM-bound there, MFMA- or HBM-bound
-        // here); forked after the latency-bound upward pass, which it would slow
-        check(hipEventRecord(h->fork_ev, s), "event record");
-        check(hipStreamWaitEvent(h->side, h->fork_ev, 0), "fork");
-        rec_begin(h, h->side, 6, &ev);
-        check(launch_product_leaf(nearp, epi, prec, h->side), "near field");
-        rec_end(h, h->side, 6, ev);
+        if (!near_early) {
+            check(hipEventRecord(h->mid_ev, s), "event record");
+            check(hipStreamWaitEvent(h->side, h->mid_ev, 0), "fork");
+            rec_begin(h, h->side, 6, &ev);
+            check(launch_product_near(nearp, y64, prec, h->side), "near field");
+            rec_end(h, h->side, 6, ev);
+        }
         check(hipEventRecord(h->join_ev, h->side), "event record");
 
         rec_begin(h, s, 3, &ev);
         if (h->rec) {
             ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, h->rt_cpl, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
             check(launch_product_store(cpl, prec, false, s), "coupling");
+            if (cut > 0) {
+                check(hipStreamWaitEvent(s, h->upper_ev, 0), "join");
+                ProductArgs cpl_b{h->d_items_cpl_b, h->n_items_cpl_b, h->rt_cpl, h->d_blks_cpl, h->d_pool_s, xh,
+                                  nullptr, yh};
+                check(launch_product_add(cpl_b, prec, false, s), "coupling");
+            }
         } else if (h->d_cgeo) {
             ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_cgeo, xh, nullptr, yh};
             check(launch_coupling_generated(cpl, m, prec, prec == P_FP32 && h->n_items_leaf > 0 ? h->cpl_lds : 0, s),
@@ -925,7 +1008,7 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
                 rec_begin(h, s, 4, &ev);
                 ProductArgs dn{h->d_items_down + h->down_off[l], h->down_off[l + 1] - h->down_off[l], h->rt_down,
                                h->d_blks_down, h->d_pool_down, yh, nullptr, yh};
-                check(launch_product_add(dn, prec, s), "downward");
+                check(launch_product_add(dn, prec, true, s), "downward");
                 rec_end(h, s, 4, ev);
             }
         } else {

@@ -2,12 +2,13 @@
 //
 //   permute      x = P u1 (node order -> cluster order) in the operator
 //                precision, plus an FP64 copy x64 on the FP32 path
+//   diagonal     y64 = D x64 + the FP64 near-singular part (cluster order)
 //   product      grouped block products Y_item = sum_b A_b X_b on MFMA 16x16x4
-//                (FP32 or FP64), used three times:
+//                (FP32 or FP64), used for:
 //                  leaf forward   xhat_s = W_s^T x|_s                     (one block per leaf)
 //                  coupling       yhat_t = sum_{s admissible} S_ts xhat_s  (one item per cluster)
-//                  leaf output    y|_t = V_t yhat_t + sum_{s near} K_ts x|_s, then
-//                                 y64 = y + D x64 (+ FP64 near-singular part), cluster order
+//                  near field     y64|_t += sum_{s near} K_ts x|_s
+//                  leaf output    y64|_t += V_t yhat_t
 //   upward       xhat_t = sum_c E_c^T xhat_c     (Kronecker mode products, per level)
 //   downward     yhat_c += E_c yhat_parent        (top levels along paths, then per level)
 //   unpermute    u2 = P^T y64
@@ -77,7 +78,7 @@ __device__ inline int xcd_item_of(int v, int n_items) {     // v: index in the g
 
 __device__ inline int xcd_item(int n_items) { return xcd_item_of(int(blockIdx.x), n_items); }
 
-enum { EPI_STORE = 0, EPI_LEAF = 1, EPI_ADD64 = 2, EPI_ADD = 3 };
+enum { EPI_STORE = 0, EPI_ADD64 = 2, EPI_ADD = 3 };
 
 template <typename V>
 __device__ inline V ld(const unsigned char* base, unsigned byte_off) {
@@ -217,7 +218,7 @@ __device__ inline void accumulate_live(int live, const ItemDesc& it, const BlkDe
 // barriers inside are reached by all waves (waves with nothing left to store
 // leave only after the last one).
 template <typename T, int RTW, int NRG, int EPI>
-__device__ inline void product_item(const ProductArgs& a, const LeafEpilogue& epi, int item, T* red) {
+__device__ inline void product_item(const ProductArgs& a, double* y64, int item, T* red) {
     typedef typename Mfma<T>::acc acc_t;
     constexpr int NBG = kWaves / NRG;
     const ItemDesc it = a.items[item];
@@ -250,7 +251,7 @@ __device__ inline void product_item(const ProductArgs& a, const LeafEpilogue& ep
 #pragma unroll
                     for (int v = 0; v < 4; ++v) acc[r][v] += slot[(r * 4 + v) * 64 + lane];
             }
-        if (EPI != EPI_LEAF && bg > 0) return;
+        if (bg > 0) return;
     }
 
     const int M = it.m;
@@ -261,64 +262,85 @@ __device__ inline void product_item(const ProductArgs& a, const LeafEpilogue& ep
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
-                if (row < M) epi.y64[(int64_t(it.out_row) + row) * RHS_TILE + q] += double(acc[r][v]);
+                if (row < M) y64[(int64_t(it.out_row) + row) * RHS_TILE + q] += double(acc[r][v]);
             }
         return;
     }
-    if (EPI == EPI_STORE || EPI == EPI_ADD) {       // y = acc, or y += acc in the operator precision
+    // y = acc, or y += acc in the operator precision
 #pragma unroll
-        for (int r = 0; r < RTW; ++r)
+    for (int r = 0; r < RTW; ++r)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
-                if (row < M) {
-                    T* o = static_cast<T*>(a.y) + (int64_t(it.out_row) + row) * RHS_TILE + q;
-                    *o = EPI == EPI_ADD ? *o + acc[r][v] : acc[r][v];
-                }
+        for (int v = 0; v < 4; ++v) {
+            const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
+            if (row < M) {
+                T* o = static_cast<T*>(a.y) + (int64_t(it.out_row) + row) * RHS_TILE + q;
+                *o = EPI == EPI_ADD ? *o + acc[r][v] : acc[r][v];
             }
-        return;
-    }
-    // leaf output: stage the item's rows in LDS, then every thread finishes
-    // some (row, column) pairs in FP64: y + D x64 + near-singular part
-    T* stage = red + (NBG - 1) * NRG * RTW * 256;
-    if (bg == 0) {
-#pragma unroll
-        for (int r = 0; r < RTW; ++r)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = 16 * (rg * RTW + r) + Mfma<T>::row(lane >> 4, v);
-                if (row < M) stage[row * RHS_TILE + q] = acc[r][v];
-            }
-    }
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < M * RHS_TILE; idx += kThreads) {
-        const int row = idx >> 4, col = idx & 15;
-        const int64_t pos = int64_t(it.out_row) + row;
-        const int64_t o = pos * RHS_TILE + col;
-        double y = double(stage[idx]) + epi.diag[pos] * epi.x64[o];
-        if (epi.ns_off != nullptr) {
-            const int64_t e0 = epi.ns_off[pos], e1 = epi.ns_off[pos + 1];
-            double s0 = 0.0, s1 = 0.0;
-            int64_t e = e0;
-            for (; e + 2 <= e1; e += 2) {
-                const int32_t p0 = epi.ns_pos[e], p1 = epi.ns_pos[e + 1];
-                s0 += epi.ns_val[e] * epi.x64[int64_t(p0) * RHS_TILE + col];
-                s1 += epi.ns_val[e + 1] * epi.x64[int64_t(p1) * RHS_TILE + col];
-            }
-            if (e < e1) s0 += epi.ns_val[e] * epi.x64[int64_t(epi.ns_pos[e]) * RHS_TILE + col];
-            y += s0 + s1;
         }
-        epi.y64[o] = y;
-    }
 }
 
 // One item per workgroup, grid xcd_grid(n).
 template <typename T, int RTW, int NRG, int EPI>
-__global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, LeafEpilogue epi) {
+__global__ void __launch_bounds__(kThreads) k_product(ProductArgs a, double* y64) {
     extern __shared__ unsigned char smem_raw[];
     T* red = reinterpret_cast<T*>(smem_raw);
     const int item = xcd_item(a.n_items);
-    if (item >= 0) product_item<T, RTW, NRG, EPI>(a, epi, item, red);
+    if (item >= 0) product_item<T, RTW, NRG, EPI>(a, y64, item, red);
+}
+
+// y64 = D x64 + sum over the node's near-singular pairs of w x64 (FP64), for
+// every cluster position and all 16 columns: the part of the near field that
+// stays in FP64 when the blocks are stored in lower precision (ns_off NULL:
+// D x64 alone).  One thread per (position, 4 columns): each pair's position
+// and weight are loaded once per 4 columns, the x64 rows as two 16-byte loads,
+// four pairs in flight.
+__global__ void __launch_bounds__(256) k_diag_nearsing(int64_t n, LeafEpilogue e) {
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    const int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t pos = t >> 2;
+    const int c0 = int(t & 3) * 4;
+    if (pos >= n) return;
+    const double d = e.diag[pos];
+    const d2* xr = reinterpret_cast<const d2*>(e.x64 + pos * RHS_TILE + c0);
+    const d2 xa = xr[0], xb = xr[1];
+    d2 ya = d * xa, yb = d * xb;
+    if (e.ns_off != nullptr) {
+        const int64_t e1 = e.ns_off[pos + 1];
+        d2 sa = {0.0, 0.0}, sb = {0.0, 0.0};
+        int64_t q = e.ns_off[pos];
+        for (; q + 4 <= e1; q += 4) {
+            int32_t p[4];
+            double w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                p[j] = e.ns_pos[q + j];
+                w[j] = e.ns_val[q + j];
+            }
+            d2 ua[4], ub[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const d2* xs = reinterpret_cast<const d2*>(e.x64 + int64_t(p[j]) * RHS_TILE + c0);
+                ua[j] = xs[0];
+                ub[j] = xs[1];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sa += w[j] * ua[j];
+                sb += w[j] * ub[j];
+            }
+        }
+        for (; q < e1; ++q) {
+            const double w = e.ns_val[q];
+            const d2* xs = reinterpret_cast<const d2*>(e.x64 + int64_t(e.ns_pos[q]) * RHS_TILE + c0);
+            sa += w * xs[0];
+            sb += w * xs[1];
+        }
+        ya += sa;
+        yb += sb;
+    }
+    d2* yr = reinterpret_cast<d2*>(e.y64 + pos * RHS_TILE + c0);
+    yr[0] = ya;
+    yr[1] = yb;
 }
 
 // Coupling products yhat_t = sum_s S_ts xhat_s for orders with k <= 128.  Every
@@ -1022,22 +1044,19 @@ inline int pow2ceil(int v) {
 }
 
 template <typename T, int EPI>
-hipError_t dispatch(const ProductArgs& a, const LeafEpilogue& e, int rtw, int nrg, hipStream_t st) {
+hipError_t dispatch(const ProductArgs& a, double* y64, int rtw, int nrg, hipStream_t st) {
     const unsigned grid = a.n_items > 0 ? xcd_grid(a.n_items) : 0u;
     if (grid == 0) return hipSuccess;
     const int nbg = kWaves / nrg;
-    size_t lds = size_t(nbg - 1) * nrg * rtw * 256 * sizeof(T);
-    if (EPI == EPI_LEAF) lds += size_t(16 * rtw) * RHS_TILE * sizeof(T);   // staged output rows
-#define H2DLP_CASE(RTW_, NRG_)                                                                       \
-    if (rtw == RTW_ && nrg == NRG_) {                                                                \
-        hipLaunchKernelGGL((k_product<T, RTW_, NRG_, EPI>), dim3(grid), dim3(kThreads), lds, st, a, e); \
-        return hipGetLastError();                                                                    \
+    const size_t lds = size_t(nbg - 1) * nrg * rtw * 256 * sizeof(T);
+#define H2DLP_CASE(RTW_, NRG_)                                                                         \
+    if (rtw == RTW_ && nrg == NRG_) {                                                                  \
+        hipLaunchKernelGGL((k_product<T, RTW_, NRG_, EPI>), dim3(grid), dim3(kThreads), lds, st, a, y64); \
+        return hipGetLastError();                                                                      \
     }
     H2DLP_CASE(1, 1) H2DLP_CASE(2, 1) H2DLP_CASE(4, 1) H2DLP_CASE(8, 1)
-    if (EPI != EPI_LEAF) {
-        H2DLP_CASE(1, 2) H2DLP_CASE(2, 2) H2DLP_CASE(4, 2) H2DLP_CASE(8, 2)
-        H2DLP_CASE(1, 4) H2DLP_CASE(2, 4) H2DLP_CASE(4, 4) H2DLP_CASE(8, 4)
-    }
+    H2DLP_CASE(1, 2) H2DLP_CASE(2, 2) H2DLP_CASE(4, 2) H2DLP_CASE(8, 2)
+    H2DLP_CASE(1, 4) H2DLP_CASE(2, 4) H2DLP_CASE(4, 4) H2DLP_CASE(8, 4)
 #undef H2DLP_CASE
     return hipErrorInvalidValue;
 }
@@ -1112,9 +1131,8 @@ hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows
         rtw = pow2ceil((rt + nrg - 1) / nrg);
     }
     if (rtw > 8) return hipErrorInvalidValue;
-    LeafEpilogue none{};
-    if (prec == P_FP64) return dispatch<double, EPI_STORE>(a, none, rtw, nrg, st);
-    return dispatch<float, EPI_STORE>(a, none, rtw, nrg, st);
+    if (prec == P_FP64) return dispatch<double, EPI_STORE>(a, nullptr, rtw, nrg, st);
+    return dispatch<float, EPI_STORE>(a, nullptr, rtw, nrg, st);
 }
 
 hipError_t launch_coupling_generated(const ProductArgs& a, int m, int prec, size_t lds_floor, hipStream_t st) {
@@ -1188,14 +1206,19 @@ hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_product_add(const ProductArgs& a, int prec, hipStream_t st) {
+hipError_t launch_product_add(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st) {
     const int rt = a.rt;
-    const int nrg = rt >= 4 ? 4 : pow2ceil(rt);       // one block per item: the waves split its rows
-    const int rtw = pow2ceil((rt + nrg - 1) / nrg);
+    int nrg, rtw;
+    if (prefer_rows) {
+        nrg = rt >= 4 ? 4 : pow2ceil(rt);
+        rtw = pow2ceil((rt + nrg - 1) / nrg);
+    } else {
+        nrg = rt <= 8 ? 1 : (rt <= 16 ? 2 : 4);
+        rtw = pow2ceil((rt + nrg - 1) / nrg);
+    }
     if (rtw > 8) return hipErrorInvalidValue;
-    LeafEpilogue none{};
-    if (prec == P_FP64) return dispatch<double, EPI_ADD>(a, none, rtw, nrg, st);
-    return dispatch<float, EPI_ADD>(a, none, rtw, nrg, st);
+    if (prec == P_FP64) return dispatch<double, EPI_ADD>(a, nullptr, rtw, nrg, st);
+    return dispatch<float, EPI_ADD>(a, nullptr, rtw, nrg, st);
 }
 
 hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hipStream_t st) {
@@ -1203,17 +1226,22 @@ hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hip
     const int nrg = rt >= 4 ? 4 : pow2ceil(rt);       // one block per item: the waves split its rows
     const int rtw = pow2ceil((rt + nrg - 1) / nrg);
     if (rtw > 8) return hipErrorInvalidValue;
-    LeafEpilogue e{};
-    e.y64 = y64;
-    if (prec == P_FP64) return dispatch<double, EPI_ADD64>(a, e, rtw, nrg, st);
-    return dispatch<float, EPI_ADD64>(a, e, rtw, nrg, st);
+    if (prec == P_FP64) return dispatch<double, EPI_ADD64>(a, y64, rtw, nrg, st);
+    return dispatch<float, EPI_ADD64>(a, y64, rtw, nrg, st);
 }
 
-hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st) {
+hipError_t launch_product_near(const ProductArgs& a, double* y64, int prec, hipStream_t st) {
     const int rtw = pow2ceil(a.rt);
     if (rtw > 8) return hipErrorInvalidValue;
-    if (prec == P_FP64) return dispatch<double, EPI_LEAF>(a, e, rtw, 1, st);
-    return dispatch<float, EPI_LEAF>(a, e, rtw, 1, st);
+    if (prec == P_FP64) return dispatch<double, EPI_ADD64>(a, y64, rtw, 1, st);
+    return dispatch<float, EPI_ADD64>(a, y64, rtw, 1, st);
+}
+
+hipError_t launch_diag_nearsing(const LeafEpilogue& e, int64_t n_pos, hipStream_t st) {
+    if (n_pos <= 0) return hipSuccess;
+    const int64_t blocks = (n_pos * 4 + 255) / 256;
+    hipLaunchKernelGGL(k_diag_nearsing, dim3(unsigned(blocks)), dim3(256), 0, st, n_pos, e);
+    return hipGetLastError();
 }
 
 hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, const int32_t* child1, const void* e,

@@ -58,7 +58,7 @@ hipError_t launch_build_near(DevMesh mesh, const NearDesc* near, int64_t n_near,
 
 // ---------------------------------------------------------------- apply
 
-struct LeafEpilogue {           // y64 = y + D x64 (+ near-singular FP64 part), cluster order
+struct LeafEpilogue {           // y64 = D x64 (+ near-singular FP64 part), cluster order
     const double* diag;         // by cluster position
     const double* x64;          // FP64 input rows (cluster order, 16 columns)
     double* y64;                // FP64 output rows (cluster order, 16 columns)
@@ -84,14 +84,17 @@ hipError_t launch_unpermute(const double* y64, int io, int64_t n_nodes, int nr, 
                             hipStream_t st);
 // prefer_rows: split the rows of one item over the 4 waves (else split its blocks)
 hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st);
-hipError_t launch_product_leaf(const ProductArgs& a, const LeafEpilogue& e, int prec, hipStream_t st);
+// y64 = D x64 + the FP64 near-singular part, over n_pos cluster positions (all 16 columns)
+hipError_t launch_diag_nearsing(const LeafEpilogue& e, int64_t n_pos, hipStream_t st);
+// near field: y64 += sum_b A_b X_b of each leaf item, the waves splitting its blocks
+hipError_t launch_product_near(const ProductArgs& a, double* y64, int prec, hipStream_t st);
 // Coupling products; for k <= 128 with ceil(k/16) a power of two the blocks are
 // stored k x coupling_cols(k) (zero columns beyond k) and a pipelined kernel runs.
 hipError_t launch_coupling(const ProductArgs& a, int k, int prec, hipStream_t st);
-// y += sum_b A_b X_b of each item, in the operator precision (the split of
-// rows over waves as with prefer_rows; y may be the source array, at rows
-// other than the item's)
-hipError_t launch_product_add(const ProductArgs& a, int prec, hipStream_t st);
+// y += sum_b A_b X_b of each item, in the operator precision (prefer_rows as
+// for launch_product_store; y may be the source array, at rows other than the
+// item's)
+hipError_t launch_product_add(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st);
 // y64 += sum_b A_b X_b of each item (FP64 accumulation target in cluster order)
 hipError_t launch_product_add64(const ProductArgs& a, double* y64, int prec, hipStream_t st);
 // Generated coupling (orders 1..5, FP32 or FP64): a.pool holds the per-cluster
