@@ -32,7 +32,8 @@ KERNEL_SOURCES = ("paper_1811_05731_amd/csrc/apply_kernels.hip", "paper_1811_057
                   "paper_1811_05731_amd/csrc/kernels.h", "paper_1811_05731_amd/csrc/api.cpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sphere_l8.json")
 RHS_PER_PASS = 16
-DEFAULT_COUPLING = "generated"
+DEFAULT_COUPLING = "stored"
+DEFAULT_RECOMPRESS_EPS = 1e-6
 
 
 def kernel_hash() -> str:
@@ -75,7 +76,7 @@ def case_rhs(case, xyz):
     return rhs.normal_rhs(n, case.nrhs, 0), f"{case.nrhs} N(0,1) right-hand sides"
 
 
-def describe(case, n, n_tri, rhs_text, dense_far_max=0, coupling="stored"):
+def describe(case, n, n_tri, rhs_text, dense_far_max=0, coupling="stored", recompress_eps=0.0):
     m = case.mesh
     if m.kind == "icosphere":
         geo = f"icosphere level {m.level}, radial jitter +-{m.jitter:g}"
@@ -84,21 +85,25 @@ def describe(case, n, n_tri, rhs_text, dense_far_max=0, coupling="stored"):
     else:
         geo = m.kind
     rep = (f"coupling matrices {'recomputed in the apply' if coupling == 'generated' else 'stored'}"
-           + (f", admissible blocks with |t||s| <= {dense_far_max} kept exact" if dense_far_max else ""))
+           + (f", admissible blocks with |t||s| <= {dense_far_max} kept exact" if dense_far_max else "")
+           + (f", bases recompressed to adaptive ranks (relative tolerance {recompress_eps:g})" if recompress_eps
+              else ""))
     return (f"{case.name}: {geo}, {n} boundary nodes, {n_tri} triangles, order {case.order}, leaf {case.leaf}, "
             f"eta {case.eta:g}, {rhs_text}; {rep}")
 
 
 def coupling_alg_bytes(st, elem_s: int, elem_v: int) -> int:
     """Algorithmic bytes of one coupling launch: every S_ts once (elem_s bytes
-    per entry), xhat read once and yhat written once (elem_v bytes per value)."""
-    return st.coupling_entries * elem_s + 2 * st.n_clusters * st.k * 16 * elem_v
+    per entry), xhat read once and yhat written once (elem_v bytes per value;
+    the ranks summed over the clusters are C k without recompression)."""
+    return st.coupling_entries * elem_s + (st.rank_sum_col + st.rank_sum_row) * 16 * elem_v
 
 
 def apply_alg_bytes(st, elem: int, n_nodes: int, nrhs: int, io_elem: int = 8) -> int:
     """Algorithmic bytes of one apply: the stored operator once, plus compulsory vectors."""
     operator = st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer
-    vectors = 8 * n_nodes + 4 * n_nodes + 2 * io_elem * n_nodes * nrhs + 2 * 2 * st.n_clusters * st.k * 16 * elem
+    vectors = (8 * n_nodes + 4 * n_nodes + 2 * io_elem * n_nodes * nrhs
+               + 2 * (st.rank_sum_col + st.rank_sum_row) * 16 * elem)
     return operator + vectors
 
 
@@ -338,18 +343,24 @@ def oracle_direct(case_name: str, cores: int, dense_far_max: int = 0, reps: int 
             "note": f"coupling matrices cached after the first apply; BLAS at {cores} threads"}
 
 
-def cpu_baseline(xyz, tri, case, nrhs: int, dense_far_max: int, direct_c2: bool = True) -> dict:
+def cpu_baseline(xyz, tri, case, nrhs: int, dense_far_max: int, direct_c2: bool = True,
+                 recompress_eps: float = 0.0) -> dict:
     """The CPU oracle beside the GPU: the benchmarked operator on a sample
     (`value`), the 2562-node sphere timed directly (dense matvec and whole H2
     apply, median of 3) and, unless disabled, the 163842-node sphere's whole
     apply timed directly."""
     from threadpoolctl import threadpool_limits
 
-    from oracle import dense, h2
+    from oracle import dense, h2, recompress
     from workloads import cases, rhs
     host = host_cpu()
     cores = host["cores"]
     out = oracle_sample(xyz, tri, case, nrhs, dense_far_max, cores)
+    if recompress_eps:
+        out["operator"] = ("the oracle's interpolation H2 matrix of the same mesh (the matrix the recompressed "
+                           "operator approximates to the tolerance; the oracle's own recompression of 655362 "
+                           "nodes takes far longer than a baseline may); its recompressed apply is timed "
+                           "directly at 2562 nodes under direct.sphere_l4")
     out["cpu_model"] = host["model"]
     out["visible_cpus"] = host["visible_cpus"]
     c1 = cases.CASES["sphere_l4"]
@@ -358,8 +369,14 @@ def cpu_baseline(xyz, tri, case, nrhs: int, dense_far_max: int, direct_c2: bool 
     u = np.vstack([rhs.z_rhs(x1), rhs.normal_rhs(x1.shape[0], 1, 0)])
     H1 = h2.H2Oracle(x1, t1, order=c1.order, leaf=c1.leaf, eta=c1.eta)
     H1.apply(u)                                            # builds the pieces once
+    R1 = None
+    if recompress_eps:
+        t0 = time.perf_counter()
+        R1 = recompress.Recompressed(H1, recompress_eps)
+        R1.apply(u)
+        t_r1 = time.perf_counter() - t0
     with threadpool_limits(limits=cores):
-        td, th = [], []
+        td, th, tr = [], [], []
         for _ in range(3):
             t0 = time.perf_counter()
             _ = u @ M.T
@@ -367,18 +384,29 @@ def cpu_baseline(xyz, tri, case, nrhs: int, dense_far_max: int, direct_c2: bool 
             t0 = time.perf_counter()
             H1.apply(u)
             th.append(time.perf_counter() - t0)
+            if R1 is not None:
+                t0 = time.perf_counter()
+                R1.apply(u)
+                tr.append(time.perf_counter() - t0)
     del M, H1
     out["direct"] = {"sphere_l4": {"nodes": int(x1.shape[0]), "rhs": 2, "dense_matvec_s_median": float(np.median(td)),
                                    "h2_apply_s_median": round(float(np.median(th)), 4),
                                    "h2_GDOF_s": x1.shape[0] * 2 / float(np.median(th)) / 1e9}}
+    if R1 is not None:
+        out["direct"]["sphere_l4"].update({"recompressed_apply_s_median": round(float(np.median(tr)), 4),
+                                           "recompressed_GDOF_s": x1.shape[0] * 2 / float(np.median(tr)) / 1e9,
+                                           "recompression_build_s": round(t_r1, 2),
+                                           "recompress_eps": recompress_eps})
     if direct_c2:
         c2 = cases.CASES["sphere_l7"]
-        out["direct"]["sphere_l7"] = oracle_direct("sphere_l7", cores, default_dense_far_max(c2.order, DEFAULT_COUPLING))
+        # the plain interpolation matrix when the benchmarked operator is its recompression
+        dmax_c2 = 0 if recompress_eps else default_dense_far_max(c2.order, DEFAULT_COUPLING)
+        out["direct"]["sphere_l7"] = oracle_direct("sphere_l7", cores, dmax_c2)
     return out
 
 
 def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4, coupling: str = "stored",
-                dense_far: bool = False) -> dict:
+                dense_far: bool = False, recompress_eps: float = 0.0) -> dict:
     """The serving mix: Poisson arrivals of 1..16-column requests over six resident meshes.
 
     Spheres (levels 4-7), the thin film and a torus, FP32 operators; the HBM
@@ -393,7 +421,8 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4,
     for spec, order, leaf in cases.SERVING_MESHES:
         xyz, tri = cases.mesh_of(spec)
         specs.append(serving.MeshSpec(spec.name, xyz, tri, order=order, leaf=leaf, eta=2.0, precision="fp32",
-                                      coupling=coupling, dense_far_max=order ** 6 if dense_far else 0))
+                                      coupling=coupling, dense_far_max=order ** 6 if dense_far else 0,
+                                      recompress_eps=recompress_eps))
     srv = serving.Server(backend, 0, n_slots=n_slots, max_batch_rhs=64)
     for s in specs:
         srv.add_mesh(s)
@@ -418,6 +447,7 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4,
             "budget_GB": round(budget / 1e9, 2), "operators_GB": round(sum(resident) / 1e9, 2),
             "slots_GB": round(srv.fixed_bytes() / 1e9, 2),
             "slots": n_slots, "precision": "fp32", "coupling": coupling, "dense_far_max": "k^2" if dense_far else 0,
+            "recompress_eps": recompress_eps,
             "rate_hz": rate_hz, "prewarm_s": round(prewarm_s, 2),
             "reloads": sum(st["reloads"].values()), "offloads": sum(st["offloads"].values()),
             "breakdown_ms": st["breakdown_ms"]}
@@ -432,9 +462,12 @@ def coupling_flops(st) -> float:
 
 
 def near_field_alg_bytes(st, elem: int, n_nodes: int) -> int:
-    """Algorithmic bytes of one near-field launch (16 columns): the near blocks
-    and FP64 near-singular entries once, x (and x64 on the FP32 path) read, y64 written."""
-    vec = n_nodes * RHS_PER_PASS * (elem + 8 + (8 if elem == 4 else 0))
+    """Algorithmic bytes of the near-field pair of launches (16 columns): the
+    diagonal kernel reads x64 and D and the FP64 near-singular entries and
+    writes y64; the near-field product reads its blocks and x once and adds
+    into y64 (read and written).  st.bytes_near holds the blocks, the
+    near-singular entries and their offsets."""
+    vec = n_nodes * RHS_PER_PASS * (8 + 8 + elem + 16) + 8 * n_nodes
     return st.bytes_near + vec
 
 
@@ -477,7 +510,7 @@ def apply_roofline(st, prec: str, n_nodes: int, nrhs: int, ms: float, coupling: 
     apply_alg_bytes."""
     elem = 8 if prec == "fp64" else 4
     b = apply_alg_bytes(st, elem, n_nodes, nrhs)
-    entries = st.coupling_entries + st.near_entries + st.dense_far_entries + 2 * n_nodes * st.k
+    entries = st.coupling_entries + st.near_entries + st.dense_far_entries + st.bytes_bases // elem
     f = 2.0 * entries * nrhs
     peak = MFMA_PEAK_TFS["fp64" if prec == "fp64" else "fp32"]
     t_b, t_f = b / HBM_PEAK_GBS / 1e6, f / peak / 1e9
@@ -493,9 +526,10 @@ def rel_err(a, ref) -> float:
 
 def other_workload(name: str, configs, steps: int = 10, warmup: int = 2, dense_rows=None) -> dict:
     """Time and check the named workload in each (precision, coupling,
-    dense_far_max) of `configs` with its own right-hand sides; each result
-    against the FP64 result of the same operator, and against exact dense rows
-    when given (rows, values)."""
+    dense_far_max, recompress_eps) of `configs` with its own right-hand sides;
+    each result against the FP64 result of the same operator (a recompressed
+    one also against the FP64 interpolation matrix), and against exact dense
+    rows when given (rows, values)."""
     import torch
 
     from paper_1811_05731_amd import h2dlp
@@ -505,20 +539,30 @@ def other_workload(name: str, configs, steps: int = 10, warmup: int = 2, dense_r
     d1 = torch.tensor(u1, device="cuda:0")
     d2 = torch.empty_like(d1)
     res, outs = {"workload": describe(case, n, tri.shape[0], rhs_text), "nodes": n, "rhs": u1.shape[0]}, {}
-    for prec, cpl, dmax in configs:
+
+    def key(prec, cpl, dmax, eps):
+        return f"{prec}_{cpl}_{dmax}" + (f"_recompressed_{eps:g}" if eps else "")
+
+    for prec, cpl, dmax, eps in configs:
         op = h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
-                            coupling=cpl, dense_far_max=dmax)
+                            coupling=cpl, dense_far_max=dmax, recompress_eps=eps)
         ms, _ = time_path(op, d1, d2, steps, warmup, None)
-        outs[(prec, cpl, dmax)] = d2.cpu().numpy()
-        res[f"{prec}_{cpl}_{dmax}"] = {"value": round(n * u1.shape[0] / (ms * 1e-3) / 1e9, 4),
-                                      "ms_per_step": round(ms, 4),
-                                      "resident_GB": round(op.stats.bytes_resident / 1e9, 3)}
+        outs[(prec, cpl, dmax, eps)] = d2.cpu().numpy()
+        res[key(prec, cpl, dmax, eps)] = {"value": round(n * u1.shape[0] / (ms * 1e-3) / 1e9, 4),
+                                          "ms_per_step": round(ms, 4),
+                                          "resident_GB": round(op.stats.bytes_resident / 1e9, 3)}
         op.close()
-    for (prec, cpl, dmax), val in outs.items():
-        rec = res[f"{prec}_{cpl}_{dmax}"]
-        ref = next((v for (p, c, d), v in outs.items() if p == "fp64" and d == dmax), None)
+    for (prec, cpl, dmax, eps), val in outs.items():
+        rec = res[key(prec, cpl, dmax, eps)]
+        # against the FP64 result of the same operator (same exact-block
+        # threshold and recompression tolerance)
+        ref = next((v for (p, c, d, e), v in outs.items() if p == "fp64" and d == dmax and e == eps), None)
         if ref is not None and prec != "fp64":
             rec["vs_fp64_gpu_rel_err"] = rel_err(val, ref)
+        if eps:
+            ref0 = next((v for (p, c, d, e), v in outs.items() if p == "fp64" and d == 0 and e == 0), None)
+            if ref0 is not None:
+                rec["vs_fp64_interpolation_rel_err"] = rel_err(val, ref0)
         if dense_rows is not None:
             rows, vals = dense_rows
             rec["vs_dense_rows_rel_err"] = [float(f"{e:.3e}") for e in
@@ -537,6 +581,9 @@ def main():
     ap.add_argument("--dense-far-max", type=int, default=-1,
                     help="admissible blocks with |t||s| <= this are stored exactly (0: the plain H2 matrix; "
                          "-1: where that is cheaper -- k^2 with stored coupling, k^2/2 with generated coupling)")
+    ap.add_argument("--recompress-eps", type=float, default=DEFAULT_RECOMPRESS_EPS,
+                    help="recompress the bases to adaptive ranks at this relative tolerance (0: the interpolation "
+                         "bases); needs stored coupling")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-cpu-c2", action="store_true", help="skip the direct oracle apply at 163842 nodes")
     ap.add_argument("--no-variants", action="store_true", help="skip the other precisions and coupling modes")
@@ -567,12 +614,17 @@ def main():
     def dmax_of(coupling):
         return args.dense_far_max if args.dense_far_max >= 0 else default_dense_far_max(case.order, coupling)
 
-    def build(prec, coupling, dmax=None):
+    rec_eps = args.recompress_eps
+    if rec_eps > 0 and args.dense_far_max < 0:
+        dense_far_max = 0                          # the recompression replaces the exact small blocks
+
+    def build(prec, coupling, dmax=None, eps=0.0):
         return h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
-                              coupling=coupling, dense_far_max=dmax_of(coupling) if dmax is None else dmax)
+                              coupling=coupling, dense_far_max=dmax_of(coupling) if dmax is None else dmax,
+                              recompress_eps=eps)
 
     t0 = time.perf_counter()
-    op = build(args.precision, args.coupling)
+    op = build(args.precision, args.coupling, dense_far_max, rec_eps)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
     st = op.stats
@@ -600,7 +652,8 @@ def main():
             for rec in json.load(open(TRAFFIC_FILE))["records"]:
                 if rec.get("kernel_hash") == kernel_hash() and rec.get("kind", "coupling") == kind \
                         and rec.get("precision") == args.precision and rec.get("workload") == args.workload \
-                        and rec.get("coupling") == args.coupling and rec.get("dense_far_max", 0) == dense_far_max:
+                        and rec.get("coupling") == args.coupling and rec.get("dense_far_max", 0) == dense_far_max \
+                        and rec.get("recompress_eps", 0.0) == rec_eps:
                     roof_k["traffic"] = rec.get("bytes_per_launch")
     roof = rooflines[dominant]
     b_apply = apply_alg_bytes(st, elem, n, nrhs)
@@ -609,9 +662,10 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms, 4), "ms_per_step_median": round(ms_median, 4),
         "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32" if args.precision == "fp32" else "f64", "data": "synthetic",
-        "config": {"workload": describe(case, n, tri.shape[0], rhs_text, dense_far_max, args.coupling),
+        "config": {"workload": describe(case, n, tri.shape[0], rhs_text, dense_far_max, args.coupling, rec_eps),
                    "nodes": n, "rhs": nrhs, "order": case.order, "leaf": case.leaf, "eta": case.eta,
-                   "precision": args.precision, "coupling": args.coupling, "dense_far_max": dense_far_max},
+                   "precision": args.precision, "coupling": args.coupling, "dense_far_max": dense_far_max,
+                   "recompress_eps": rec_eps},
         "roofline": roof,
         "rooflines": rooflines,
         "apply_roofline": apply_roofline(st, args.precision, n, nrhs, ms, args.coupling),
@@ -624,6 +678,8 @@ def main():
                      "coupling_bytes": st.bytes_coupling, "near_bytes": st.bytes_near,
                      "resident_bytes": st.bytes_resident, "compression": round(st.compression, 5),
                      "bytes_per_dof": round(st.bytes_resident / n, 1),
+                     "rank_mean_row": round(st.rank_sum_row / st.n_clusters, 2),
+                     "rank_mean_col": round(st.rank_sum_col / st.n_clusters, 2),
                      "build_s": round(build_s, 2)},
         "kernel_hash": kernel_hash(),
     }
@@ -639,22 +695,28 @@ def main():
         variants, outs = {}, {}
         # each in the benchmark's configuration of its coupling mode, and the
         # plain interpolation H2 matrix (no exact admissible blocks)
-        configs = [("fp64", "stored", None), ("fp64", "generated", None), ("fp32", "stored", None),
-                   ("fp32", "generated", None), ("bf16x3", "stored", None), ("bf16x6", "stored", None),
-                   ("fp64", "generated", 0), ("fp32", "generated", 0), ("bf16x3", "stored", 0)]
-        for prec, cpl, dm in configs:
+        configs = [("fp64", "stored", None, 0.0), ("fp64", "generated", None, 0.0), ("fp32", "stored", None, 0.0),
+                   ("fp32", "generated", None, 0.0), ("bf16x3", "stored", None, 0.0), ("bf16x6", "stored", None, 0.0),
+                   ("fp64", "generated", 0, 0.0), ("fp32", "generated", 0, 0.0), ("bf16x3", "stored", 0, 0.0),
+                   ("fp64", "stored", 0, 1e-6), ("fp32", "stored", 0, 1e-6)]
+        for prec, cpl, dm, eps in configs:
             dmax = dmax_of(cpl) if dm is None else dm
-            if (prec, cpl, dmax) == (args.precision, args.coupling, dense_far_max):
+            if (prec, cpl, dmax, eps) == (args.precision, args.coupling, dense_far_max, rec_eps):
                 continue
-            if (prec.startswith("bf16") or cpl == "generated") and case.order > 5:
+            if (prec.startswith("bf16") or cpl == "generated" or eps > 0) and case.order > 5:
                 continue
-            opv = build(prec, cpl, dmax)
+            t0 = time.perf_counter()
+            opv = build(prec, cpl, dmax, eps)
+            torch.cuda.synchronize()
+            bs = time.perf_counter() - t0
             msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=("coupling",))
-            key = (prec if cpl == "stored" else f"{prec}_generated") + ("_plain" if dm == 0 and dmax == 0 else "")
+            key = ((prec if cpl == "stored" else f"{prec}_generated") + ("_plain" if dm == 0 and dmax == 0 and not eps
+                                                                        else "")
+                   + ("_recompressed" if eps else ""))
             outs[key] = d_u2.cpu().numpy()
             ev = 8 if prec == "fp64" else 4
             variants[key] = {"value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
-                             "dense_far_max": dmax,
+                             "dense_far_max": dmax, "recompress_eps": eps, "build_s": round(bs, 2),
                              "coupling": roofline_of(opv.stats, prec, cpl, kv, n),
                              "resident_GB": round(opv.stats.bytes_resident / 1e9, 2),
                              "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9
@@ -663,32 +725,42 @@ def main():
             opv.close()
         # each result against the FP64 result of the same operator (the same
         # exact-block threshold: both coupling modes give the same operator)
-        fp64_by_dmax = {}
+        # references: the FP64 result of each operator (exact-block threshold
+        # and recompression; both coupling modes give the same operator)
+        fp64_of = {}
         for key, val in outs.items():
             if key.startswith("fp64"):
-                fp64_by_dmax.setdefault(variants[key]["dense_far_max"], val)
+                fp64_of.setdefault((variants[key]["dense_far_max"], variants[key]["recompress_eps"]), val)
         if args.precision == "fp64":
-            fp64_by_dmax[dense_far_max] = u2_main
+            fp64_of[(dense_far_max, rec_eps)] = u2_main
 
-        def rel(a, dmax):
-            ref = fp64_by_dmax.get(dmax)
+        def rel(a, ref):
             return None if ref is None else rel_err(a, ref)
 
-        def rel_k(a, dmax):
+        def rel_k(a, ref):
             # the same error relative to |K u1| (without the diagonal)
-            ref = fp64_by_dmax.get(dmax)
             if ref is None:
                 return None
             k_ref = ref - diag_main[None, :] * u1
             return float(f"{np.max(np.linalg.norm(a - ref, axis=1) / np.linalg.norm(k_ref, axis=1)):.3e}")
 
         if args.precision != "fp64":
-            out["vs_fp64_gpu_rel_err"] = rel(u2_main, dense_far_max)
-            out["vs_fp64_gpu_rel_err_of_K"] = rel_k(u2_main, dense_far_max)
+            ref = fp64_of.get((dense_far_max, rec_eps))
+            out["vs_fp64_gpu_rel_err"] = rel(u2_main, ref)
+            out["vs_fp64_gpu_rel_err_of_K"] = rel_k(u2_main, ref)
+        if rec_eps:
+            # the recompressed operator against the FP64 interpolation matrix it came from
+            ref = fp64_of.get((0, 0.0))
+            out["vs_fp64_interpolation_rel_err"] = rel(u2_main, ref)
+            out["vs_fp64_interpolation_rel_err_of_K"] = rel_k(u2_main, ref)
         for key, val in outs.items():
-            if fp64_by_dmax.get(variants[key]["dense_far_max"]) is not val:
-                variants[key]["vs_fp64_gpu_rel_err"] = rel(val, variants[key]["dense_far_max"])
-                variants[key]["vs_fp64_gpu_rel_err_of_K"] = rel_k(val, variants[key]["dense_far_max"])
+            v = variants[key]
+            ref = fp64_of.get((v["dense_far_max"], v["recompress_eps"]))
+            if ref is not val:
+                v["vs_fp64_gpu_rel_err"] = rel(val, ref)
+                v["vs_fp64_gpu_rel_err_of_K"] = rel_k(val, ref)
+            if v["recompress_eps"]:
+                v["vs_fp64_interpolation_rel_err"] = rel(val, fp64_of.get((0, 0.0)))
         out["variants"] = variants
 
     if not args.no_workloads and args.workload == "sphere_l8":
@@ -696,19 +768,22 @@ def main():
         g = np.load(os.path.join(ROOT, "tests", "golden", "sphere_l7_dense_rows.npz"))
         c2 = workload("sphere_l7")[0]
         k2 = c2.order ** 6
-        out["sphere_l7"] = other_workload("sphere_l7", [("fp32", "generated", k2 // 2), ("fp64", "generated", k2 // 2),
-                                                        ("fp32", "stored", 0), ("fp64", "stored", 0)],
+        out["sphere_l7"] = other_workload("sphere_l7", [("fp32", "generated", k2 // 2, 0.0),
+                                                        ("fp64", "generated", k2 // 2, 0.0),
+                                                        ("fp32", "stored", 0, 0.0), ("fp64", "stored", 0, 0.0),
+                                                        ("fp32", "stored", 0, 1e-6), ("fp64", "stored", 0, 1e-6)],
                                           dense_rows=(g["rows"], g["values"]))
         c3 = workload("film")[0]
         k2 = c3.order ** 6
-        out["film"] = other_workload("film", [("fp32", "generated", k2 // 2), ("fp64", "generated", k2 // 2),
-                                              ("fp32", "stored", 0), ("fp64", "stored", 0)])
+        out["film"] = other_workload("film", [("fp32", "generated", k2 // 2, 0.0), ("fp64", "generated", k2 // 2, 0.0),
+                                              ("fp32", "stored", 0, 0.0), ("fp64", "stored", 0, 0.0),
+                                              ("fp32", "stored", 0, 1e-6), ("fp64", "stored", 0, 1e-6)])
 
     if not args.no_serve:
         print("# serving the mixed request stream", file=sys.stderr, flush=True)
-        # serving keeps operators small (reloads cross PCIe): generated coupling
-        # without exact admissible blocks
-        out["serving"] = serve_bench(coupling=args.coupling, dense_far=False)
+        # serving keeps operators small (reloads cross PCIe): the benchmarked
+        # representation without exact admissible blocks
+        out["serving"] = serve_bench(coupling=args.coupling, dense_far=False, recompress_eps=rec_eps)
 
     if args.copy_calibration:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)        # 1 GiB
@@ -720,7 +795,8 @@ def main():
 
     if not args.no_cpu:
         print("# timing the CPU oracle", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(xyz, tri, case, nrhs, dense_far_max, direct_c2=not args.no_cpu_c2)
+        out["cpu_baseline"] = cpu_baseline(xyz, tri, case, nrhs, dense_far_max, direct_c2=not args.no_cpu_c2,
+                                           recompress_eps=rec_eps)
     print(json.dumps(out), flush=True)
 
 

@@ -40,6 +40,7 @@ class MeshSpec:
     precision: str = "fp32"
     coupling: str = "stored"          # "stored" | "generated" (coupling matrices recomputed in the apply)
     dense_far_max: int = 0            # admissible blocks with |t||s| <= this kept as exact entries
+    recompress_eps: float = 0.0       # > 0: bases recompressed to adaptive ranks at this tolerance (stored coupling)
 
     @property
     def n_nodes(self) -> int:
@@ -120,12 +121,17 @@ class GpuBackend(Backend):
 
     def plan_bytes(self, spec):
         p = self.h2dlp.plan(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
-                            coupling=spec.coupling, dense_far_max=spec.dense_far_max)
+                            coupling=spec.coupling, dense_far_max=spec.dense_far_max,
+                            recompress_eps=spec.recompress_eps)
         return p.stats.bytes_resident, p.stats.workspace_bytes
 
     def build(self, spec):
         return self.h2dlp.Operator(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
-                                   device=self.dev_index, coupling=spec.coupling, dense_far_max=spec.dense_far_max)
+                                   device=self.dev_index, coupling=spec.coupling, dense_far_max=spec.dense_far_max,
+                                   recompress_eps=spec.recompress_eps)
+
+    def built_bytes(self, op):
+        return op.stats.bytes_resident
 
     def offload(self, op):
         op.offload()
@@ -289,6 +295,11 @@ class Server:
         if m.op is None:
             m.op = self.backend.build(m.spec)
             m.builds += 1
+            # a recompressed operator's ranks are known only once built: the
+            # plan's count (full ranks) is an upper bound, the built one is exact
+            built = getattr(self.backend, "built_bytes", None)
+            if built is not None:
+                m.resident_bytes = min(m.resident_bytes, int(built(m.op)))
         else:
             self.backend.reload(m.op, slot)
             m.reloads += 1

@@ -17,7 +17,8 @@ def test_default_thresholds():
 
 
 def test_coupling_records():
-    st = types.SimpleNamespace(coupling_entries=10 * 125 ** 2, n_clusters=7, k=125)
+    st = types.SimpleNamespace(coupling_entries=10 * 125 ** 2, n_clusters=7, k=125, rank_sum_row=7 * 125,
+                               rank_sum_col=7 * 125)
     # generated: 2 flops per entry and right-hand side, 16 right-hand sides per pass
     flops = 2.0 * 10 * 125 ** 2 * 16
     assert bench.coupling_flops(st) == flops
@@ -40,11 +41,13 @@ def test_coupling_records():
 
 def test_near_field_record():
     st = types.SimpleNamespace(bytes_near=10 ** 6)
-    # FP32: x (4 B), x64 (8 B) read and y64 (8 B) written per node and column
-    assert bench.near_field_alg_bytes(st, 4, 100) == 10 ** 6 + 100 * 16 * 20
-    assert bench.near_field_alg_bytes(st, 8, 100) == 10 ** 6 + 100 * 16 * 16
+    # per node and column: x64 (8 B) read and y64 (8 B) written by the
+    # diagonal kernel, x (operator precision) read and y64 read and written by
+    # the near-field product; D (8 B) per node
+    assert bench.near_field_alg_bytes(st, 4, 100) == 10 ** 6 + 100 * 16 * 36 + 800
+    assert bench.near_field_alg_bytes(st, 8, 100) == 10 ** 6 + 100 * 16 * 40 + 800
     r = bench.near_field_roofline(st, "fp32", {"near_field": (3.0, 3)}, 100)
-    assert r["bound"] == "hbm" and abs(r["achieved"] - (10 ** 6 + 32000) / 1e-3 / 1e9) < 0.1
+    assert r["bound"] == "hbm" and abs(r["achieved"] - (10 ** 6 + 57600 + 800) / 1e-3 / 1e9) < 0.1
 
 
 def test_more_than_one_gpu_is_refused():
@@ -56,7 +59,7 @@ def test_more_than_one_gpu_is_refused():
 def test_apply_roofline_record():
     st = types.SimpleNamespace(bytes_coupling=0, bytes_near=4 * 10 ** 6, bytes_bases=4 * 2 * 100 * 8,
                                bytes_transfer=0, n_clusters=3, k=8, coupling_entries=10 ** 9, near_entries=10 ** 6,
-                               dense_far_entries=0)
+                               dense_far_entries=0, rank_sum_row=24, rank_sum_col=24)
     r = bench.apply_roofline(st, "fp32", 100, 16, 1.0, "generated")
     flops = 2.0 * (10 ** 9 + 10 ** 6 + 2 * 100 * 8) * 16
     assert r["alg_flops"] == flops and r["bound"] == "mfma"

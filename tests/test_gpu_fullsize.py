@@ -307,3 +307,29 @@ def test_film_fp32_smooth_fields(lib, film, coupling, dmax):
         # amplified rounding sits in the larger coplanar admissible blocks
         assert np.max(err) <= 6e-6, err
         pytest.xfail(f"film FP32 misses 1e-6 (measured {np.max(err):.2e})")
+
+
+def test_film_recompressed_fp32(lib, film):
+    # the recompressed operator (Section 4, tolerance 1e-6) on the four smooth
+    # fields: its orthonormal bases carry no cancelling terms across the thin
+    # boxes, so FP32 holds 1e-6 against FP64 here; both stay within the
+    # recompression's own error of the FP64 interpolation matrix
+    c, xyz, tri = film
+    u = rhs.smooth_fields(xyz, c.nrhs)
+    eps = 1e-6
+    ref_op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision="fp64", coupling="generated")
+    ref = run(ref_op, u)
+    d = ref_op.export_diagonal()
+    ref_op.close()
+    outs = {}
+    for prec in ("fp64", "fp32"):
+        op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec, recompress_eps=eps)
+        outs[prec] = run(op, u)
+        op.close()
+    err = relerr(outs["fp32"], outs["fp64"])
+    err_i = relerr(outs["fp32"], ref)
+    err_k = relerr(outs["fp64"] - d[None, :] * u, ref - d[None, :] * u)
+    print(f"film recompressed: fp32 vs fp64 {np.array2string(err, precision=2)}, vs the FP64 interpolation matrix "
+          f"{err_i.max():.2e} (fp64 of K u: {err_k.max():.2e})")
+    assert np.all(err <= 1e-6) and np.all(err_i <= 1e-6), (err, err_i)
+    assert np.all(err_k <= 10 * eps), err_k
