@@ -219,6 +219,24 @@ int h2dlp_offload(h2dlp_handle h);
 int h2dlp_reload(h2dlp_handle h);
 int h2dlp_reload_ex(h2dlp_handle h, void* stream);
 
+/* Persistence (Section 6.1: the H2 matrix is computed once per geometry,
+ * stored to a file and read back at later starts instead of being rebuilt).
+ * h2dlp_save writes a built operator (an offloaded one too) to `path`: its
+ * mesh, build options, the host state its recompression derived and every
+ * device buffer, in host byte order.  EINVAL: the handle comes from
+ * h2dlp_plan, or the file cannot be written; EDEVICE: a device copy failed.
+ * h2dlp_load restores such a file on `device` (-1: the current device)
+ * without building: the host structure is planned again from the stored mesh
+ * and options (it is deterministic) and the device buffers are copied from the
+ * file, so applies give the saved operator's results bit for bit.  *out
+ * receives a handle like h2dlp_build_ex's (NULL on error).  EINVAL: path
+ * missing or unreadable, not an operator file, truncated or inconsistent with
+ * its own mesh; ENOTSUP: written by another version of this library, or the
+ * device is not a gfx950; ENOMEM: device or pinned host memory ran out.  The
+ * file is this library's own layout, not an exchange format. */
+int h2dlp_save(h2dlp_handle h, const char* path);
+int h2dlp_load(const char* path, int device, h2dlp_handle* out);
+
 void h2dlp_free(h2dlp_handle h);
 
 const char* h2dlp_last_error(void);

@@ -195,7 +195,8 @@ struct h2dlp_ctx {
     // finishes levels above up_cut on side2; the rest (d_items_cpl_b) add
     ItemDesc* d_items_cpl_b = nullptr;
     int32_t n_items_cpl_b = 0;
-    int up_cut = 0;
+    int32_t up_cut = 0;
+    int32_t n_items_v = 0;           // recompressed: leaf output items (Q_t y^_t)
     int32_t rt_fwd = 1, rt_up = 1, rt_cpl = 1, rt_down = 1;
     h2dlp_stats st{};
     // profiling
@@ -701,6 +702,7 @@ void recompress_impl(h2dlp_ctx* h, const double* d_boxes, const double* wt64, co
     h->d_items_down = h->upload(items_down, kept, stream);
     h->d_blks_down = h->upload(blks_down, kept, stream);
     h->d_items_v = h->upload(h->items_v, kept, stream);
+    h->n_items_v = int32_t(h->items_v.size());
     h->d_blks_v = h->upload(blks_v, kept, stream);
     h->n_items_fwd = int32_t(h->items_fwd.size());
     h->n_items_cpl = int32_t(h->items_cpl.size());
@@ -724,6 +726,34 @@ void recompress_impl(h2dlp_ctx* h, const double* d_boxes, const double* wt64, co
     st.rank_max_col = *std::max_element(rc.begin(), rc.end());
     const double h2_bytes = double(st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer);
     st.compression = 1.0 - h2_bytes / (8.0 * double(S.n_nodes) * double(S.n_nodes));
+}
+
+// The handle's own streams and events (created once: an apply creates none) and
+// the device's LDS figures for the generated coupling's occupancy shaping.
+void make_streams(h2dlp_ctx* h) {
+    check(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "side stream");
+    check(hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking), "side stream");
+    check(hipEventCreateWithFlags(&h->cut_ev, hipEventDisableTiming), "event");
+    check(hipEventCreateWithFlags(&h->upper_ev, hipEventDisableTiming), "event");
+    check(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming), "event");
+    check(hipEventCreateWithFlags(&h->mid_ev, hipEventDisableTiming), "event");
+    check(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming), "event");
+    int dev = 0, lds_cu = 0, lds_wg = 0;
+    check(hipGetDevice(&dev), "device");
+    check(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev), "attribute");
+    check(hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
+    h->cpl_lds = size_t(std::max(0, std::min(lds_cu / 4, lds_wg)));
+}
+
+// The end of a build or a load: which buffers are empty, host descriptors dropped.
+void finish_materialize(h2dlp_ctx* h) {
+    h->empty_field.clear();
+    for (auto& f : h->fields()) h->empty_field.push_back(*f.first == nullptr);
+    h->leaves.clear(); h->leaves.shrink_to_fit();
+    h->vleaves.clear(); h->vleaves.shrink_to_fit();
+    h->fars.clear(); h->fars.shrink_to_fit();
+    h->nears.clear(); h->nears.shrink_to_fit();
+    h->materialized = true;
 }
 
 // Device part of a build: upload, generate every block in FP64 arithmetic, free the build-only arrays.
@@ -762,20 +792,7 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     h->d_items_leaf = h->upload(h->items_leaf, &kept, stream);
     h->d_blks_leaf = h->upload(h->blks_leaf, &kept, stream);
     h->d_items_near = h->upload(h->items_near, &kept, stream);
-    check(hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking), "side stream");
-    check(hipStreamCreateWithFlags(&h->side2, hipStreamNonBlocking), "side stream");
-    check(hipEventCreateWithFlags(&h->cut_ev, hipEventDisableTiming), "event");
-    check(hipEventCreateWithFlags(&h->upper_ev, hipEventDisableTiming), "event");
-    check(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming), "event");
-    check(hipEventCreateWithFlags(&h->mid_ev, hipEventDisableTiming), "event");
-    check(hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming), "event");
-    {
-        int dev = 0, lds_cu = 0, lds_wg = 0;
-        check(hipGetDevice(&dev), "device");
-        check(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev), "attribute");
-        check(hipDeviceGetAttribute(&lds_wg, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "attribute");
-        h->cpl_lds = size_t(std::max(0, std::min(lds_cu / 4, lds_wg)));
-    }
+    make_streams(h);
     if (!fp64) {
         h->d_ns_off = h->upload(S.ring_off, &kept, stream);
         h->d_ns_pos = h->upload(S.ring_pos, &kept, stream);
@@ -828,18 +845,81 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     for (void* p : temp) h->release(p);
     h->d_ws = h->alloc<void>(h->ws_bytes, &kept);
     if (rec) h->st.bytes_resident = kept;
-    h->empty_field.clear();
-    for (auto& f : h->fields()) h->empty_field.push_back(*f.first == nullptr);
-    // host-side descriptors are no longer needed
-    h->leaves.clear(); h->leaves.shrink_to_fit();
-    h->vleaves.clear(); h->vleaves.shrink_to_fit();
-    h->fars.clear(); h->fars.shrink_to_fit();
-    h->nears.clear(); h->nears.shrink_to_fit();
-    h->materialized = true;
+    finish_materialize(h);
     return H2DLP_OK;
 }
 
 h2dlp_ctx* as_ctx(h2dlp_handle h) { return reinterpret_cast<h2dlp_ctx*>(h); }
+
+// *dev: a HIP ordinal, or -1 for the current device; it must be a gfx950
+int pick_device(int* dev) {
+    if (*dev < 0 && hipGetDevice(dev) != hipSuccess) return fail(H2DLP_ENOTSUP, "no HIP device");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || *dev >= ndev) return fail(H2DLP_ENOTSUP, "no such HIP device");
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, *dev) != hipSuccess) return fail(H2DLP_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(H2DLP_ENOTSUP, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
+    return H2DLP_OK;
+}
+
+// ---------------------------------------------------------------- persistence
+// An operator file (host byte order): magic, format, the library's count of
+// device buffers and size of h2dlp_stats; the build options; the mesh; the
+// host state that a recompressed build derives from its ranks; the stats;
+// then every buffer of fields() in order as (scratch flag, bytes, contents),
+// a scratch buffer by its size only.  Loading plans the mesh again (the host
+// structure is deterministic) and takes the device buffers from the file.
+constexpr char kFileMagic[8] = {'H', '2', 'D', 'L', 'P', 'O', 'P', 'S'};
+constexpr uint32_t kFileFormat = 1;
+constexpr size_t kStage = size_t(64) << 20;     // bytes per copy through pinned host memory
+
+struct FileOut {
+    FILE* f = nullptr;
+    bool ok = true;
+    ~FileOut() { if (f) std::fclose(f); }
+    void raw(const void* p, size_t n) { if (ok && n && std::fwrite(p, 1, n, f) != n) ok = false; }
+    template <typename T> void pod(const T& v) { raw(&v, sizeof v); }
+    template <typename T> void vec(const std::vector<T>& v) {
+        pod(uint64_t(v.size()));
+        raw(v.data(), v.size() * sizeof(T));
+    }
+};
+
+struct FileIn {
+    FILE* f = nullptr;
+    bool ok = true;
+    uint64_t left = 0;                          // bytes of the file not read yet
+    ~FileIn() { if (f) std::fclose(f); }
+    void raw(void* p, size_t n) {
+        if (!ok || n == 0) return;
+        if (n > left || std::fread(p, 1, n, f) != n) { ok = false; return; }
+        left -= n;
+    }
+    template <typename T> T pod() { T v{}; raw(&v, sizeof v); return v; }
+    template <typename T> void vec(std::vector<T>& v) {
+        const uint64_t n = pod<uint64_t>();
+        if (!ok || n > left / sizeof(T)) { ok = false; return; }
+        v.resize(size_t(n));
+        raw(v.data(), size_t(n) * sizeof(T));
+    }
+};
+
+struct PinnedStage {
+    void* p = nullptr;
+    ~PinnedStage() { if (p) (void)hipHostFree(p); }
+};
+
+// state a recompressed build derives from its ranks (plan values otherwise)
+template <bool READ, typename IO>
+void derived_state(IO& io, h2dlp_ctx* h) {
+    for (std::vector<int32_t>* v : {&h->rank_row, &h->rank_col, &h->up_off, &h->up_end, &h->down_off}) io.vec(*v);
+    for (int32_t* x : {&h->up_cut, &h->n_items_cpl_b, &h->rt_fwd, &h->rt_up, &h->rt_cpl, &h->rt_down,
+                       &h->n_items_fwd, &h->n_items_cpl, &h->n_items_v}) {
+        if constexpr (READ) *x = io.template pod<int32_t>();
+        else io.pod(*x);
+    }
+}
 
 // The kernels dereference u1, u2 and the workspace.  Refuse a pointer that is
 // not device memory of the handle's GPU, or whose allocation ends before
@@ -1027,7 +1107,7 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
 
         // join, then y64 += V_t yhat_t and back to the caller's node order
         check(hipStreamWaitEvent(s, h->join_ev, 0), "join");
-        ProductArgs leafv = h->rec ? ProductArgs{h->d_items_v, int32_t(h->items_v.size()), h->rt_leaf, h->d_blks_v,
+        ProductArgs leafv = h->rec ? ProductArgs{h->d_items_v, h->n_items_v, h->rt_leaf, h->d_blks_v,
                                                  h->d_pool_q, x, yh, nullptr}
                                    : ProductArgs{h->d_items_v, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf,
                                                  h->d_pool_leaf, x, yh, nullptr};
@@ -1108,13 +1188,8 @@ int h2dlp_build_ex(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle*
     std::unique_ptr<h2dlp_ctx> h(as_ctx(*out));
     *out = nullptr;
     int dev = o->device;
-    if (dev < 0 && hipGetDevice(&dev) != hipSuccess) return fail(H2DLP_ENOTSUP, "no HIP device");
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) return fail(H2DLP_ENOTSUP, "no such HIP device");
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return fail(H2DLP_EDEVICE, "hipGetDeviceProperties failed");
-    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
-        return fail(H2DLP_ENOTSUP, std::string("device is ") + prop.gcnArchName + ", library built for gfx950");
+    rc = pick_device(&dev);
+    if (rc != H2DLP_OK) return rc;
     int cur = 0;
     if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(dev) != hipSuccess) return fail(H2DLP_EDEVICE, "hipSetDevice failed");
     h->device = dev;
@@ -1367,6 +1442,155 @@ int h2dlp_reload(h2dlp_handle hh) {
     if (hipEventSynchronize(h->ready) != hipSuccess) return fail(H2DLP_EDEVICE, "waiting for the reload failed");
     h->ready_pending = false;
     return H2DLP_OK;
+}
+
+int h2dlp_save(h2dlp_handle hh, const char* path) {
+    h2dlp_ctx* h = as_ctx(hh);
+    if (!h) return fail(H2DLP_EINVAL, "handle is NULL");
+    if (!path) return fail(H2DLP_EINVAL, "path is NULL");
+    if (!h->materialized) return fail(H2DLP_EINVAL, "handle comes from h2dlp_plan: nothing to save");
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (hipSetDevice(h->device) != hipSuccess) return fail(H2DLP_EDEVICE, "hipSetDevice failed");
+    auto done = [&](int rc) { (void)hipSetDevice(cur); return rc; };
+    if (h->ready_pending && hipEventSynchronize(h->ready) != hipSuccess)
+        return done(fail(H2DLP_EDEVICE, "waiting for the reload failed"));
+    FileOut o;
+    o.f = std::fopen(path, "wb");
+    if (!o.f) return done(fail(H2DLP_EINVAL, std::string("cannot open ") + path + " for writing"));
+    auto fs = h->fields();
+    o.raw(kFileMagic, sizeof kFileMagic);
+    o.pod(kFileFormat);
+    o.pod(uint32_t(fs.size()));
+    o.pod(uint32_t(sizeof(h2dlp_stats)));
+    const h2dlp_options& op = h->opt;
+    o.pod(int32_t(op.order)); o.pod(int32_t(op.leaf)); o.pod(op.eta); o.pod(int32_t(op.precision));
+    o.pod(op.alpha); o.pod(int32_t(op.coupling)); o.pod(op.dense_far_max); o.pod(op.recompress_eps);
+    o.vec(h->S.xyz);
+    o.vec(h->S.tri);
+    derived_state<false>(o, h);
+    o.pod(uint64_t(h->ws_xh));
+    o.pod(uint64_t(h->ws_bytes));
+    o.pod(h->st);
+    PinnedStage stage;
+    if (!h->offloaded && hipHostMalloc(&stage.p, kStage, hipHostMallocDefault) != hipSuccess) {
+        stage.p = nullptr;
+        return done(fail(H2DLP_ENOMEM, "pinned host allocation failed"));
+    }
+    for (auto& f : fs) {
+        const void* dev = *f.first;
+        const void* host = nullptr;
+        size_t bytes = 0;
+        if (h->offloaded) {        // the parked host copy is the operator
+            for (const auto& pk : h->parked)
+                if (pk.field == f.first) { bytes = pk.bytes; host = pk.host; }
+        } else if (dev) {
+            bytes = h->bytes_of(const_cast<void*>(dev));
+        }
+        o.pod(uint8_t(f.second));
+        o.pod(uint64_t(bytes));
+        if (f.second) continue;
+        for (size_t off = 0; off < bytes && o.ok; off += kStage) {
+            const size_t n = std::min(kStage, bytes - off);
+            if (host) {
+                o.raw(static_cast<const char*>(host) + off, n);
+            } else {
+                if (hipMemcpy(stage.p, static_cast<const char*>(dev) + off, n, hipMemcpyDeviceToHost) != hipSuccess)
+                    return done(fail(H2DLP_EDEVICE, "copy to host failed"));
+                o.raw(stage.p, n);
+            }
+        }
+    }
+    if (!o.ok || std::fflush(o.f) != 0) return done(fail(H2DLP_EINVAL, std::string("writing ") + path + " failed"));
+    return done(H2DLP_OK);
+}
+
+int h2dlp_load(const char* path, int device, h2dlp_handle* out) {
+    if (!out) return fail(H2DLP_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(H2DLP_EINVAL, "path is NULL");
+    FileIn in;
+    in.f = std::fopen(path, "rb");
+    if (!in.f) return fail(H2DLP_EINVAL, std::string("cannot open ") + path);
+    if (std::fseek(in.f, 0, SEEK_END) != 0) return fail(H2DLP_EINVAL, "cannot size the file");
+    const long size = std::ftell(in.f);
+    if (size < 0 || std::fseek(in.f, 0, SEEK_SET) != 0) return fail(H2DLP_EINVAL, "cannot size the file");
+    in.left = uint64_t(size);
+    char magic[sizeof kFileMagic] = {};
+    in.raw(magic, sizeof magic);
+    if (!in.ok || std::memcmp(magic, kFileMagic, sizeof magic) != 0)
+        return fail(H2DLP_EINVAL, std::string(path) + " is not an h2dlp operator file");
+    const uint32_t format = in.pod<uint32_t>(), n_fields = in.pod<uint32_t>(), stats_size = in.pod<uint32_t>();
+    if (format != kFileFormat || stats_size != sizeof(h2dlp_stats))
+        return fail(H2DLP_ENOTSUP, "operator file written by another version of the library");
+    h2dlp_options o;
+    h2dlp_default_options(&o);
+    o.order = in.pod<int32_t>(); o.leaf = in.pod<int32_t>(); o.eta = in.pod<double>();
+    o.precision = in.pod<int32_t>(); o.alpha = in.pod<double>(); o.coupling = in.pod<int32_t>();
+    o.dense_far_max = in.pod<int64_t>(); o.recompress_eps = in.pod<double>();
+    o.device = device;
+    std::vector<double> xyz;
+    std::vector<int32_t> tri;
+    in.vec(xyz);
+    in.vec(tri);
+    if (!in.ok || xyz.size() % 3 != 0 || tri.size() % 3 != 0) return fail(H2DLP_EINVAL, "truncated operator file");
+    const h2dlp_mesh mesh{int64_t(xyz.size() / 3), xyz.data(), int64_t(tri.size() / 3), tri.data()};
+    h2dlp_handle planned = nullptr;
+    int rc = h2dlp_plan(&mesh, &o, &planned);       // the host structure, exactly as the build had it
+    if (rc != H2DLP_OK) return rc;
+    std::unique_ptr<h2dlp_ctx> h(as_ctx(planned));
+    const size_t ws_xh_plan = h->ws_xh, ws_plan = h->ws_bytes;
+    derived_state<true>(in, h.get());
+    const size_t ws_xh = size_t(in.pod<uint64_t>()), ws_bytes = size_t(in.pod<uint64_t>());
+    const h2dlp_stats st = in.pod<h2dlp_stats>();
+    auto fs = h->fields();
+    if (!in.ok) return fail(H2DLP_EINVAL, "truncated operator file");
+    if (n_fields != fs.size()) return fail(H2DLP_ENOTSUP, "operator file written by another version of the library");
+    if (!h->rec && (ws_xh != ws_xh_plan || ws_bytes != ws_plan))
+        return fail(H2DLP_EINVAL, "operator file does not match the plan of its own mesh and options");
+    int dev = device;
+    rc = pick_device(&dev);
+    if (rc != H2DLP_OK) return rc;
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess || hipSetDevice(dev) != hipSuccess)
+        return fail(H2DLP_EDEVICE, "hipSetDevice failed");
+    h->device = dev;
+    auto done = [&](int r) { (void)hipSetDevice(cur); return r; };
+    try {
+        h->ws_xh = ws_xh;
+        h->ws_bytes = ws_bytes;
+        PinnedStage stage;
+        if (hipHostMalloc(&stage.p, kStage, hipHostMallocDefault) != hipSuccess) {
+            stage.p = nullptr;
+            throw std::bad_alloc();
+        }
+        int64_t kept = 0;
+        for (auto& f : fs) {
+            const bool scratch = in.pod<uint8_t>() != 0;
+            const uint64_t bytes = in.pod<uint64_t>();
+            if (!in.ok || scratch != f.second || (!scratch && bytes > in.left))
+                return done(fail(H2DLP_EINVAL, "truncated or corrupt operator file"));
+            if (scratch || bytes == 0) continue;
+            void* d = h->alloc<void>(size_t(bytes), &kept);
+            *f.first = d;
+            for (size_t off = 0; off < bytes; off += kStage) {
+                const size_t n = std::min<size_t>(kStage, size_t(bytes) - off);
+                in.raw(stage.p, n);
+                if (!in.ok) return done(fail(H2DLP_EINVAL, "truncated operator file"));
+                check(hipMemcpy(static_cast<char*>(d) + off, stage.p, n, hipMemcpyHostToDevice), "copy to device");
+            }
+        }
+        h->d_ws = h->alloc<void>(h->ws_bytes, &kept);
+        make_streams(h.get());
+        h->st = st;                                 // the built operator's figures, ranks included
+        finish_materialize(h.get());
+    } catch (const HipError& e) {
+        return done(fail(H2DLP_EDEVICE, e.where + ": " + hipGetErrorString(e.err)));
+    } catch (const std::bad_alloc&) {
+        return done(fail(H2DLP_ENOMEM, "device or host allocation failed"));
+    }
+    *out = reinterpret_cast<h2dlp_handle>(h.release());
+    return done(H2DLP_OK);
 }
 
 void h2dlp_free(h2dlp_handle hh) { delete as_ctx(hh); }

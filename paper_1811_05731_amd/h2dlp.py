@@ -63,7 +63,7 @@ class _Stats(ctypes.Structure):
 
 EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
             "h2dlp_bytes", "h2dlp_info", "h2dlp_export_structure", "h2dlp_export_diagonal", "h2dlp_offload",
-            "h2dlp_reload", "h2dlp_reload_ex", "h2dlp_free", "h2dlp_apply_noalloc",
+            "h2dlp_reload", "h2dlp_reload_ex", "h2dlp_free", "h2dlp_apply_noalloc", "h2dlp_save", "h2dlp_load",
             "h2dlp_last_error", "h2dlp_profile", "h2dlp_profile_read")
 
 
@@ -90,6 +90,10 @@ def _load():
     lib.h2dlp_apply_ex.restype = I
     lib.h2dlp_apply_noalloc.argtypes = [V, V, V, I, I, V]
     lib.h2dlp_apply_noalloc.restype = I
+    lib.h2dlp_save.argtypes = [V, ctypes.c_char_p]
+    lib.h2dlp_save.restype = I
+    lib.h2dlp_load.argtypes = [ctypes.c_char_p, I, P(V)]
+    lib.h2dlp_load.restype = I
     lib.h2dlp_bytes.argtypes = [V, P(ctypes.c_size_t), P(ctypes.c_size_t)]
     lib.h2dlp_bytes.restype = I
     lib.h2dlp_info.argtypes = [V, P(_Stats)]
@@ -201,6 +205,31 @@ class Operator:
             self.device = device if device >= 0 else torch.cuda.current_device()
         self.n_nodes = xyz.shape[0]
         self.stats = self.info()
+
+    @classmethod
+    def load(cls, path, device: int = -1):
+        """An operator restored from a file written by save() (h2dlp_load): no
+        build, the device buffers come from the file."""
+        h = ctypes.c_void_p()
+        _check(_lib.h2dlp_load(os.fsencode(path), int(device), ctypes.byref(h)))
+        op = cls.__new__(cls)
+        op._h = h
+        op._free = _lib.h2dlp_free
+        op.plan_only = False
+        if device >= 0:
+            op.device = device
+        else:
+            import torch
+            op.device = torch.cuda.current_device()
+        op.stats = op.info()
+        op.n_nodes = int(op.stats.n_nodes)
+        return op
+
+    def save(self, path):
+        """Write the built operator to `path` (h2dlp_save), for Operator.load."""
+        if self.plan_only:
+            raise ValueError("a planned operator has nothing to save")
+        _check(_lib.h2dlp_save(self._h, os.fsencode(path)))
 
     def close(self):
         if getattr(self, "_h", None):

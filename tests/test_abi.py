@@ -193,3 +193,33 @@ def test_recompression_arguments():
     # before the build the plan reports the interpolation sizes, an upper bound
     assert p.stats.rank_sum_row == p.stats.n_clusters * 27 and p.stats.rank_max_col == 27
     assert p.stats.n_far == q.stats.n_far and p.stats.coupling_entries == q.stats.coupling_entries
+
+
+def test_persistence_errors(tmp_path):
+    # h2dlp_save / h2dlp_load refuse what they cannot use before touching a device
+    lib = h2dlp.library()
+    xyz, tri = meshes.icosphere(2)
+    op = h2dlp.plan(xyz, tri)
+    assert lib.h2dlp_save(op.handle, str(tmp_path / "x.op").encode()) == h2dlp.EINVAL   # nothing on a device
+    assert lib.h2dlp_save(None, b"x") == h2dlp.EINVAL
+    with pytest.raises(ValueError):
+        op.save(tmp_path / "x.op")
+    out = ctypes.c_void_p(1)
+    assert lib.h2dlp_load(str(tmp_path / "missing.op").encode(), -1, ctypes.byref(out)) == h2dlp.EINVAL
+    assert out.value is None
+    assert lib.h2dlp_load(None, -1, ctypes.byref(out)) == h2dlp.EINVAL
+    assert lib.h2dlp_load(b"x", -1, None) == h2dlp.EINVAL
+    junk = tmp_path / "junk.op"
+    junk.write_bytes(b"not an operator file at all")
+    assert lib.h2dlp_load(str(junk).encode(), -1, ctypes.byref(out)) == h2dlp.EINVAL
+    assert "not an h2dlp operator file" in h2dlp.last_error()
+    # right magic, another format version
+    other = tmp_path / "other.op"
+    other.write_bytes(b"H2DLPOPS" + (99).to_bytes(4, "little") + bytes(64))
+    assert lib.h2dlp_load(str(other).encode(), -1, ctypes.byref(out)) == h2dlp.ENOTSUP
+    # right header, cut short inside the options
+    cut = tmp_path / "cut.op"
+    cut.write_bytes(b"H2DLPOPS" + (1).to_bytes(4, "little") + (34).to_bytes(4, "little")
+                    + ctypes.sizeof(h2dlp._Stats).to_bytes(4, "little") + bytes(10))
+    assert lib.h2dlp_load(str(cut).encode(), -1, ctypes.byref(out)) == h2dlp.EINVAL
+    assert out.value is None
