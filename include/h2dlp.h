@@ -237,6 +237,62 @@ int h2dlp_reload_ex(h2dlp_handle h, void* stream);
 int h2dlp_save(h2dlp_handle h, const char* path);
 int h2dlp_load(const char* path, int device, h2dlp_handle* out);
 
+/* Finite-element solves either side of the boundary operator: one
+ * evaluation of the magnetostatic field of a magnetised body (Section 2,
+ * eqs. u1Poiss, u1Neumann, mainInt, u2diri):
+ *     Delta u1 = div M in the body, du1/dn = M.n on its surface;
+ *     u2 = (K + D) u1 on the surface (this library's operator);
+ *     Delta u2 = 0 in the body with those values;  H = -grad (u1 + u2),
+ *     E = -(1/2) int M.H  (units mu0 = 1; M in units of Ms).
+ * Continuous P1 elements on tetrahedra, M constant per tetrahedron; u1 from
+ * the weak form int grad u1 . grad v = int M . grad v with zero node sum;
+ * both linear systems by Jacobi-preconditioned conjugate gradients in FP64
+ * on the GPU (the paper names a GPU Krylov solver for large meshes).
+ *
+ * The volume: n_nodes x 3 FP64 coordinates and n_tets x 4 node indices
+ * (0-based, either orientation, none degenerate), host memory. */
+typedef struct {
+    int64_t        n_nodes;
+    const double*  xyz;
+    int64_t        n_tets;
+    const int32_t* tet;
+} h2dlp_volume;
+
+typedef struct h2dlp_fem_ctx* h2dlp_fem;
+
+typedef struct {
+    int32_t iters_u1, iters_u2;     /* CG iterations of the two solves */
+    double  resid_u1, resid_u2;     /* final |r| / |r0| of the two solves */
+    double  energy;                 /* -(1/2) sum_t vol_t M_t . H_t */
+} h2dlp_fem_result;
+
+/* Build: the surface (faces of one tetrahedron only, oriented outward), the
+ * boundary operator on it with `opt` (order, leaf, eta, precision, coupling,
+ * dense_far_max, recompress_eps; device and stream as for h2dlp_build_ex),
+ * the P1 stiffness matrix and the element geometry.  The volume is copied.
+ * EINVAL for a bad volume (index out of range, degenerate tetrahedron, no
+ * closed surface), else the errors of h2dlp_build_ex. */
+int h2dlp_fem_build(const h2dlp_volume* vol, const h2dlp_options* opt, h2dlp_fem* out);
+/* Sizes: boundary nodes, stiffness entries, device bytes of the FEM part,
+ * and the boundary operator (owned by the handle: do not free it).  Any
+ * pointer may be NULL. */
+int h2dlp_fem_info(h2dlp_fem f, int64_t* n_boundary, int64_t* nnz, size_t* device_bytes,
+                   h2dlp_handle* boundary_op);
+/* The boundary nodes in the volume numbering, ascending (n_boundary values):
+ * the boundary operator's node j is volume node nodes[j]. */
+int h2dlp_fem_boundary_nodes(h2dlp_fem f, int64_t* nodes);
+/* One field evaluation on `stream` (a hipStream_t, NULL = null stream).
+ * m: n_tets x 3 FP64 device array (M per tetrahedron); h: n_tets x 3 FP64
+ * device array, receives H; u1, u2: n_nodes FP64 device arrays for the two
+ * potentials, or NULL.  Each solve stops at |r| <= tol |r0| or after max_iter
+ * iterations; *res (may be NULL) receives the iterations, residuals and the
+ * energy.  Returns when the evaluation is done.  EINVAL for a NULL handle,
+ * m or h, a pointer that is not device memory of the handle's GPU, tol <= 0
+ * or max_iter < 1; EDEVICE when a HIP call fails. */
+int h2dlp_fem_field(h2dlp_fem f, const double* m, double* h, double* u1, double* u2, double tol, int max_iter,
+                    void* stream, h2dlp_fem_result* res);
+void h2dlp_fem_free(h2dlp_fem f);
+
 void h2dlp_free(h2dlp_handle h);
 
 const char* h2dlp_last_error(void);

@@ -49,7 +49,9 @@ def build(verbose: bool = False) -> str:
                            ("build_kernels.hip", []),
                            ("apply_kernels.hip", []),
                            ("recompress.hip", []),
-                           ("noalloc.hip", [])):
+                           ("noalloc.hip", []),
+                           ("fem.cpp", ["-x", "c++"]),
+                           ("fem_kernels.hip", [])):
             obj = os.path.join(tmp, src + ".o")
             cmd = [hipcc, *HIP_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
             if src.endswith(".cpp"):

@@ -1226,6 +1226,12 @@ namespace h2dlp {
 
 int set_error(int code, const std::string& msg) { return fail(code, msg); }
 
+bool device_memory_ok(const void* p, size_t bytes, int dev, const char* name, std::string* why) {
+    return device_range_ok(p, bytes, dev, name, why);
+}
+
+int gfx950_device(int* dev) { return pick_device(dev); }
+
 int handle_device(h2dlp_handle hh) {
     const h2dlp_ctx* h = as_ctx(hh);
     return h && h->materialized ? h->device : -1;

@@ -11,6 +11,14 @@ namespace h2dlp {
 // Record `msg` for h2dlp_last_error() and return `code`.
 int set_error(int code, const std::string& msg);
 
+// `p` is device memory of GPU `dev` with at least `bytes` from it (else *why
+// says what is wrong).
+bool device_memory_ok(const void* p, size_t bytes, int dev, const char* name, std::string* why);
+
+// *dev: a HIP ordinal or -1 (the current device), checked to be a gfx950;
+// H2DLP_OK or an error code with its message recorded.
+int gfx950_device(int* dev);
+
 // Device ordinal of a built handle; -1 for NULL or a handle from h2dlp_plan.
 int handle_device(h2dlp_handle h);
 

@@ -1,0 +1,62 @@
+// Finite-element solves either side of the boundary operator: kernels and
+// their host-side arguments.  Internal to the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace h2dlp {
+
+constexpr int kGeo = 13;                   // doubles per tetrahedron: volume, then grad phi_0..3
+constexpr unsigned kFemBlocks = 1024;      // blocks of the reducing kernels (their partials)
+
+// slots of the device scalar array
+constexpr int kSlotRZ0 = 0;                // r . z of the current and of the next CG iteration (0, 1)
+constexpr int kSlotRR = 2;                 // r . r after the last CG iteration
+constexpr int kSlotBB = 3;                 // b . b of the system being solved
+constexpr int kSlotMean = 4;               // a mean to remove
+constexpr int kSlotEnergy = 5;             // -(1/2) sum vol M . H
+constexpr int kSlots = 8;
+
+// One preconditioned CG solve on the stiffness matrix (CSR, FP64): rows with
+// dinv = 0 are fixed (their residual is held at zero).
+struct FemCg {
+    int64_t n;
+    const int64_t* rowptr;
+    const int32_t* col;
+    const double* val;
+    const double* dinv;
+    double *r, *z, *p, *q;
+    double *part_pq, *part_rz, *part_rr;   // kFemBlocks each
+    double* S;                             // kSlots
+};
+
+hipError_t fem_geometry(int64_t n_tets, const double* xyz, const int32_t* tet, double* geo, hipStream_t st);
+hipError_t fem_stiffness(int64_t n, const int64_t* inc_off, const int32_t* inc, const int32_t* tet, const double* geo,
+                         const int64_t* rowptr, const int32_t* col, double* val, hipStream_t st);
+hipError_t fem_dinv(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, const uint8_t* on_boundary,
+                    double* dinv_free, double* dinv_fix, hipStream_t st);
+// out = s a
+hipError_t fem_scale(int64_t n, double s, const double* a, double* out, hipStream_t st);
+hipError_t fem_rhs(int64_t n, const int64_t* inc_off, const int32_t* inc, const double* geo, const double* m,
+                   double* b, hipStream_t st);
+// S[slot] = scale * (a . b)
+hipError_t fem_dot(int64_t n, const double* a, const double* b, double* part, double* S, int slot, double scale,
+                   hipStream_t st);
+// x -= S[slot]
+hipError_t fem_shift(int64_t n, double* x, const double* S, int slot, hipStream_t st);
+hipError_t fem_cg_start(const FemCg& c, const double* b, double* x, hipStream_t st);
+hipError_t fem_cg_step(const FemCg& c, double* x, int iter, hipStream_t st);
+// y = A x (the partials of x . y land in c.part_pq)
+hipError_t fem_spmv(const FemCg& c, const double* x, double* y, hipStream_t st);
+hipError_t fem_gather(int64_t nb_nodes, const int32_t* nodes, const double* u, double* ub, hipStream_t st);
+// g = 0, then g[nodes[j]] = ub[j]
+hipError_t fem_scatter(int64_t n, int64_t nb_nodes, const int32_t* nodes, const double* ub, double* g,
+                       hipStream_t st);
+hipError_t fem_axpy(int64_t n, const double* a, double s, const double* b, double* out, hipStream_t st);
+// h per tetrahedron; S[slot] = -(1/2) sum vol M . h
+hipError_t fem_field(int64_t n_tets, const int32_t* tet, const double* geo, const double* u1, const double* u2,
+                     const double* m, double* h, double* part, double* S, int slot, hipStream_t st);
+
+}  // namespace h2dlp

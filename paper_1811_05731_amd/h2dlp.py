@@ -37,6 +37,16 @@ class _Mesh(ctypes.Structure):
                 ("n_tris", ctypes.c_int64), ("tri", ctypes.POINTER(ctypes.c_int32))]
 
 
+class _Volume(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("xyz", ctypes.POINTER(ctypes.c_double)),
+                ("n_tets", ctypes.c_int64), ("tet", ctypes.POINTER(ctypes.c_int32))]
+
+
+class _FemResult(ctypes.Structure):
+    _fields_ = [("iters_u1", ctypes.c_int32), ("iters_u2", ctypes.c_int32), ("resid_u1", ctypes.c_double),
+                ("resid_u2", ctypes.c_double), ("energy", ctypes.c_double)]
+
+
 class _Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("leaf", ctypes.c_int), ("eta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("device", ctypes.c_int),
@@ -64,6 +74,7 @@ class _Stats(ctypes.Structure):
 EXPORTED = ("h2dlp_default_options", "h2dlp_build", "h2dlp_build_ex", "h2dlp_plan", "h2dlp_apply", "h2dlp_apply_ex",
             "h2dlp_bytes", "h2dlp_info", "h2dlp_export_structure", "h2dlp_export_diagonal", "h2dlp_offload",
             "h2dlp_reload", "h2dlp_reload_ex", "h2dlp_free", "h2dlp_apply_noalloc", "h2dlp_save", "h2dlp_load",
+            "h2dlp_fem_build", "h2dlp_fem_info", "h2dlp_fem_boundary_nodes", "h2dlp_fem_field", "h2dlp_fem_free",
             "h2dlp_last_error", "h2dlp_profile", "h2dlp_profile_read")
 
 
@@ -90,6 +101,16 @@ def _load():
     lib.h2dlp_apply_ex.restype = I
     lib.h2dlp_apply_noalloc.argtypes = [V, V, V, I, I, V]
     lib.h2dlp_apply_noalloc.restype = I
+    lib.h2dlp_fem_build.argtypes = [P(_Volume), P(_Options), P(V)]
+    lib.h2dlp_fem_build.restype = I
+    lib.h2dlp_fem_info.argtypes = [V, P(L), P(L), P(ctypes.c_size_t), P(V)]
+    lib.h2dlp_fem_info.restype = I
+    lib.h2dlp_fem_boundary_nodes.argtypes = [V, P(L)]
+    lib.h2dlp_fem_boundary_nodes.restype = I
+    lib.h2dlp_fem_field.argtypes = [V, V, V, V, V, D, I, V, P(_FemResult)]
+    lib.h2dlp_fem_field.restype = I
+    lib.h2dlp_fem_free.argtypes = [V]
+    lib.h2dlp_fem_free.restype = None
     lib.h2dlp_save.argtypes = [V, ctypes.c_char_p]
     lib.h2dlp_save.restype = I
     lib.h2dlp_load.argtypes = [ctypes.c_char_p, I, P(V)]
@@ -342,6 +363,79 @@ class Operator:
         n = (ctypes.c_int64 * NKINDS)()
         _check(_lib.h2dlp_profile_read(self._h, ms, n, NKINDS, int(reset)))
         return {KIND_NAMES[q]: (ms[q], n[q]) for q in range(NKINDS)}
+
+
+@dataclass
+class FemResult:
+    iters_u1: int
+    iters_u2: int
+    resid_u1: float
+    resid_u2: float
+    energy: float
+
+
+class FemField:
+    """The magnetostatic field of a magnetised body on one GPU (h2dlp_fem_*):
+    the P1 finite-element solves either side of the boundary operator."""
+
+    def __init__(self, xyz, tet, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64",
+                 alpha: float = 0.1, device: int = -1, coupling: str = "stored", dense_far_max: int = 0,
+                 recompress_eps: float = 0.0):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        tet = np.ascontiguousarray(tet, dtype=np.int32)
+        if xyz.ndim != 2 or xyz.shape[1] != 3 or tet.ndim != 2 or tet.shape[1] != 4:
+            raise ValueError("xyz must be N x 3 and tet T x 4")
+        vol = _Volume(xyz.shape[0], xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                      tet.shape[0], tet.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        opt = _Options()
+        _lib.h2dlp_default_options(ctypes.byref(opt))
+        opt.order, opt.leaf, opt.eta, opt.alpha, opt.device = order, leaf, eta, alpha, device
+        opt.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        opt.coupling = COUPLING[coupling]
+        opt.dense_far_max = int(dense_far_max)
+        opt.recompress_eps = float(recompress_eps)
+        h = ctypes.c_void_p()
+        _check(_lib.h2dlp_fem_build(ctypes.byref(vol), ctypes.byref(opt), ctypes.byref(h)))
+        self._h = h
+        self._free = _lib.h2dlp_fem_free
+        import torch
+        self.device = device if device >= 0 else torch.cuda.current_device()
+        self.n_nodes, self.n_tets = xyz.shape[0], tet.shape[0]
+        nb, nnz, nbytes, op = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_void_p()
+        _check(_lib.h2dlp_fem_info(h, ctypes.byref(nb), ctypes.byref(nnz), ctypes.byref(nbytes), ctypes.byref(op)))
+        self.n_boundary, self.nnz, self.device_bytes = nb.value, nnz.value, nbytes.value
+        self.boundary_nodes = np.empty(self.n_boundary, np.int64)
+        _check(_lib.h2dlp_fem_boundary_nodes(h, self.boundary_nodes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        s = _Stats()
+        _check(_lib.h2dlp_info(op, ctypes.byref(s)))
+        self.boundary_stats = Stats(**{f: getattr(s, f) for f, _ in _Stats._fields_})
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def field(self, m, h, u1=None, u2=None, tol: float = 1e-12, max_iter: int = 20000, stream=None) -> FemResult:
+        """H (into the device tensor h, n_tets x 3 float64) for the magnetisation m
+        (device tensor, n_tets x 3 float64); u1, u2 (device tensors, n_nodes
+        float64) receive the two potentials when given."""
+        import torch
+        for name, t, shape in (("m", m, (self.n_tets, 3)), ("h", h, (self.n_tets, 3)), ("u1", u1, (self.n_nodes,)),
+                               ("u2", u2, (self.n_nodes,))):
+            if t is None:
+                continue
+            if t.dtype != torch.float64 or tuple(t.shape) != shape:
+                raise ValueError(f"{name} must be float64 of shape {shape}")
+            if t.device.type != "cuda" or t.device.index != self.device:
+                raise ValueError(f"{name} must be on cuda:{self.device}")
+        st = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+        r = _FemResult()
+        _check(_lib.h2dlp_fem_field(self._h, _ptr(m), _ptr(h), None if u1 is None else _ptr(u1),
+                                    None if u2 is None else _ptr(u2), float(tol), int(max_iter), st, ctypes.byref(r)))
+        return FemResult(r.iters_u1, r.iters_u2, r.resid_u1, r.resid_u2, r.energy)
 
 
 def plan(xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64", alpha: float = 0.1,

@@ -223,3 +223,21 @@ def test_persistence_errors(tmp_path):
                     + ctypes.sizeof(h2dlp._Stats).to_bytes(4, "little") + bytes(10))
     assert lib.h2dlp_load(str(cut).encode(), -1, ctypes.byref(out)) == h2dlp.EINVAL
     assert out.value is None
+
+
+def test_fem_volume_errors():
+    # h2dlp_fem_build checks the volume before it touches a device
+    from workloads import volume
+    xyz, tets = volume.box_tets(1.0, 1.0, 1.0, 2, 2, 2)
+    bad = tets.copy()
+    bad[0, 1] = len(xyz)
+    flat = tets.copy()
+    flat[0, 3] = flat[0, 2]
+    for t, what in ((bad, "out of range"), (flat, "degenerate")):
+        with pytest.raises(h2dlp.H2dlpError) as e:
+            h2dlp.FemField(xyz, t)
+        assert e.value.code == h2dlp.EINVAL and what in str(e.value)
+    lib = h2dlp.library()
+    out = ctypes.c_void_p()
+    assert lib.h2dlp_fem_build(None, None, ctypes.byref(out)) == h2dlp.EINVAL
+    assert lib.h2dlp_fem_field(None, None, None, None, None, 1e-10, 10, None, None) == h2dlp.EINVAL

@@ -1,0 +1,119 @@
+"""The finite-element solves either side of the boundary operator on the GPU
+(h2dlp_fem_*; Section 2 of the paper) against the oracle's (oracle/fem.py with
+the oracle's H2 matrix as the boundary operator): the same u1, u2, H and
+energy on jittered boxes with non-uniform magnetisations, P1 exactness for a
+uniform one, and the uniformly magnetised cube's energy V/6 approached."""
+import numpy as np
+import pytest
+
+from oracle import fem, h2
+from workloads import volume
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-13          # CG stopping point, relative residual
+
+
+@pytest.fixture(scope="module")
+def lib():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1811_05731_amd import h2dlp
+    return h2dlp
+
+
+def gpu_field(lib, xyz, tets, m, **kw):
+    f = lib.FemField(xyz, tets, **kw)
+    dm = torch.tensor(m, device="cuda")
+    dh = torch.empty_like(dm)
+    u1 = torch.empty(len(xyz), dtype=torch.float64, device="cuda")
+    u2 = torch.empty_like(u1)
+    r = f.field(dm, dh, u1, u2, tol=TOL)
+    torch.cuda.synchronize()
+    out = dict(h=dh.cpu().numpy(), u1=u1.cpu().numpy(), u2=u2.cpu().numpy(), res=r, nodes=f.boundary_nodes,
+               nnz=f.nnz, bstats=f.boundary_stats)
+    f.close()
+    return out
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def h2_operator(order, leaf, eta):
+    def op(x, t, u):
+        return h2.H2Oracle(x, t, order=order, leaf=leaf, eta=eta).apply(u)
+    return op
+
+
+MESHES = {
+    "box": lambda: volume.box_tets(1.0, 2.0, 0.5, 6, 12, 3, jitter=0.2, seed=5),
+    "prism": lambda: volume.box_tets(2.0, 4.0, 0.2, 20, 40, 2, jitter=0.1, seed=6),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_fem_field_matches_the_oracle(lib, name):
+    xyz, tets = MESHES[name]()
+    m = volume.vortex_m(xyz, tets, core=0.3, seed=1)
+    ref = fem.demag(xyz, tets, m, h2_operator(4, 32, 2.0))
+    out = gpu_field(lib, xyz, tets, m, order=4, leaf=32, eta=2.0, precision="fp64")
+    assert np.array_equal(out["nodes"], ref["nodes"])
+    r = out["res"]
+    errs = dict(u1=rel(out["u1"], ref["u1"]), u2=rel(out["u2"], ref["u2"]), h=rel(out["h"], ref["h"]),
+                energy=abs(r.energy - ref["energy"]) / abs(ref["energy"]))
+    print(f"{name}: {len(tets)} tets, {len(out['nodes'])} boundary nodes, CG {r.iters_u1}/{r.iters_u2} "
+          f"iterations; vs oracle {errs}")
+    assert r.resid_u1 <= TOL and r.resid_u2 <= TOL
+    assert all(e <= 1e-9 for e in errs.values()), errs
+
+
+def test_uniform_magnetisation_is_exact_in_u1(lib):
+    xyz, tets = MESHES["box"]()
+    m = volume.uniform_m(len(tets), (0.3, -0.4, 0.866))
+    out = gpu_field(lib, xyz, tets, m, order=4, leaf=32, eta=2.0, precision="fp64")
+    lin = xyz @ m[0]
+    assert np.abs(out["u1"] - (lin - lin.mean())).max() <= 1e-10 * np.abs(lin).max()
+
+
+def test_uniformly_magnetised_cube(lib):
+    xyz, tets = volume.box_tets(1.0, 1.0, 1.0, 10, 10, 10)
+    m = volume.uniform_m(len(tets), (0.0, 0.0, 1.0))
+    out = gpu_field(lib, xyz, tets, m, order=4, leaf=32, eta=2.0, precision="fp64")
+    e = out["res"].energy
+    hz = out["h"][:, 2]
+    print(f"cube 10^3: E = {e:.6f} (V/6 = {1 / 6:.6f}), mean Hz = {hz.mean():.4f}")
+    assert abs(6.0 * e - 1.0) < 0.02                     # the oracle's 10^3 mesh: 1.4 %
+    assert abs(hz.mean() + 1.0 / 3.0) < 0.01             # H = -M/3 in the mean
+
+
+def test_lower_precision_boundary_operators(lib):
+    xyz, tets = MESHES["prism"]()
+    m = volume.vortex_m(xyz, tets, core=0.3, seed=2)
+    ref = gpu_field(lib, xyz, tets, m, order=4, leaf=32, eta=2.0, precision="fp64")
+    for kw, bound in ((dict(precision="fp32"), 1e-6), (dict(precision="fp32", coupling="generated"), 1e-6),
+                      (dict(precision="fp64", recompress_eps=1e-6), 1e-5),
+                      (dict(precision="fp32", recompress_eps=1e-6), 1e-5)):
+        out = gpu_field(lib, xyz, tets, m, order=4, leaf=32, eta=2.0, **kw)
+        e = abs(out["res"].energy - ref["res"].energy) / abs(ref["res"].energy)
+        eh = rel(out["h"], ref["h"])
+        print(f"{kw}: energy {e:.2e}, H {eh:.2e}")
+        assert e <= bound and eh <= 10 * bound, (kw, e, eh)
+
+
+def test_field_arguments_are_checked(lib):
+    xyz, tets = volume.box_tets(1.0, 1.0, 1.0, 2, 2, 2)
+    f = lib.FemField(xyz, tets, order=2, leaf=8)
+    m = torch.zeros((len(tets), 3), dtype=torch.float64, device="cuda")
+    h = torch.empty_like(m)
+    with pytest.raises(ValueError):
+        f.field(m.cpu(), h)
+    with pytest.raises(ValueError):
+        f.field(m.float(), h)
+    with pytest.raises(ValueError):
+        f.field(m[:-1], h)
+    with pytest.raises(lib.H2dlpError):
+        f.field(m, h, tol=0.0)
+    r = f.field(m, h)                                     # zero magnetisation: zero field
+    assert r.energy == 0.0 and float(h.abs().max()) == 0.0
+    f.close()
