@@ -453,6 +453,57 @@ def serve_bench(n_requests: int = 512, rate_hz: float = 200.0, n_slots: int = 4,
             "breakdown_ms": st["breakdown_ms"]}
 
 
+def fem_bench(reps: int = 3) -> dict:
+    """Whole field evaluations (Section 2: the Neumann solve for u1, the boundary
+    operator, the Dirichlet solve for u2, H and the energy) on a 10:20:1
+    rectangular prism, the paper's test body, cut into 100 x 200 x 10 cells of
+    six tetrahedra (1.2 million tetrahedra, seeded interior jitter of 0.1
+    cell).  The boundary operator is the benchmarked representation (FP32,
+    recompressed at 1e-6; order 4, leaf 64).  Uniform magnetisations along
+    the three axes give the demagnetising factors; their sum should be 1."""
+    import torch
+
+    from paper_1811_05731_amd import h2dlp
+    from workloads import volume
+    lx, ly, lz, nx, ny, nz = 2.0, 4.0, 0.2, 100, 200, 10
+    xyz, tets = volume.box_tets(lx, ly, lz, nx, ny, nz, jitter=0.1, seed=0)
+    t0 = time.perf_counter()
+    f = h2dlp.FemField(xyz, tets, order=4, leaf=64, eta=2.0, precision="fp32", recompress_eps=1e-6)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    vol = lx * ly * lz
+    dh = torch.empty((len(tets), 3), dtype=torch.float64, device="cuda")
+    out = {"workload": f"prism {lx:g} x {ly:g} x {lz:g} (10:20:1), {nx} x {ny} x {nz} cells of 6 tetrahedra, "
+                       "interior jitter 0.1 cell; boundary operator FP32 recompressed at 1e-6, order 4, leaf 64",
+           "nodes": int(len(xyz)), "tets": int(len(tets)), "boundary_nodes": int(f.n_boundary),
+           "stiffness_entries": int(f.nnz), "build_s": round(build_s, 2),
+           "boundary_operator_GB": round(f.boundary_stats.bytes_resident / 1e9, 3),
+           "fem_device_GB": round(f.device_bytes / 1e9, 3)}
+    factors = {}
+    for axis, d in (("x", (1, 0, 0)), ("y", (0, 1, 0)), ("z", (0, 0, 1))):
+        dm = torch.tensor(volume.uniform_m(len(tets), d), device="cuda")
+        ts, r = [], None
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = f.field(dm, dh, tol=1e-10)
+            ts.append(time.perf_counter() - t0)
+        factors[axis] = 2.0 * r.energy / vol
+        out[f"uniform_{axis}"] = {"energy": r.energy, "demag_factor": round(factors[axis], 6),
+                                  "cg_iterations": [r.iters_u1, r.iters_u2],
+                                  "field_ms_median": round(1e3 * float(np.median(ts)), 2)}
+    out["demag_factor_sum"] = round(sum(factors.values()), 6)
+    dm = torch.tensor(volume.vortex_m(xyz, tets, core=0.2, seed=0), device="cuda")
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        r = f.field(dm, dh, tol=1e-10)
+        ts.append(time.perf_counter() - t0)
+    out["vortex"] = {"energy": r.energy, "cg_iterations": [r.iters_u1, r.iters_u2],
+                     "field_ms_median": round(1e3 * float(np.median(ts)), 2)}
+    f.close()
+    return out
+
+
 MFMA_PEAK_TFS = {"fp32": 157.3, "fp64": 78.6}     # dense MFMA peaks of MI355X
 
 
@@ -590,6 +641,7 @@ def main():
     ap.add_argument("--no-workloads", action="store_true", help="skip the 163842-node sphere and the film")
     ap.add_argument("--copy-calibration", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving run")
+    ap.add_argument("--no-fem", action="store_true", help="skip the finite-element field evaluations")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -778,6 +830,10 @@ def main():
         out["film"] = other_workload("film", [("fp32", "generated", k2 // 2, 0.0), ("fp64", "generated", k2 // 2, 0.0),
                                               ("fp32", "stored", 0, 0.0), ("fp64", "stored", 0, 0.0),
                                               ("fp32", "stored", 0, 1e-6), ("fp64", "stored", 0, 1e-6)])
+
+    if not args.no_fem and args.workload == "sphere_l8":
+        print("# finite-element field evaluations", file=sys.stderr, flush=True)
+        out["fem"] = fem_bench()
 
     if not args.no_serve:
         print("# serving the mixed request stream", file=sys.stderr, flush=True)
