@@ -11,7 +11,8 @@
 // Field (per magnetisation): right side, Jacobi-preconditioned CG for u1
 // (zero node sum), u2 on the boundary through the boundary operator, CG for
 // u2 on the interior nodes, H per tetrahedron and the energy, all on the
-// caller's stream; the host only reads the residual every few iterations.
+// caller's stream; the host only reads the residual every few iterations,
+// and each run of iterations between two reads is one replayed HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -46,7 +47,7 @@ constexpr int kCheckEvery = 8;   // CG iterations between two reads of the resid
 
 struct h2dlp_fem_ctx {
     int device = -1;
-    int64_t n = 0, n_tets = 0, nnz = 0;
+    int64_t n = 0, n_tets = 0, nnz = 0, ell_entries = 0;
     std::vector<int32_t> bnodes;             // boundary nodes (volume numbering), ascending
     h2dlp_handle bop = nullptr;              // the boundary operator on the surface of bnodes
     std::vector<void*> bufs;
@@ -55,9 +56,10 @@ struct h2dlp_fem_ctx {
     double* d_geo = nullptr;
     int64_t* d_inc_off = nullptr;
     int32_t* d_inc = nullptr;
-    int64_t* d_rowptr = nullptr;
-    int32_t* d_col = nullptr;
-    double* d_val = nullptr;
+    int64_t* d_ell_off = nullptr;            // the stiffness matrix in sliced ELL (fem.h)
+    int32_t* d_ell_w = nullptr;
+    int32_t* d_ell_col = nullptr;
+    double* d_ell_val = nullptr;
     double* d_dinv_free = nullptr;
     double* d_dinv_fix = nullptr;
     int32_t* d_bnode = nullptr;
@@ -65,6 +67,11 @@ struct h2dlp_fem_ctx {
     double *d_u1 = nullptr, *d_u2 = nullptr, *d_g = nullptr, *d_ub1 = nullptr, *d_ub2 = nullptr;
     double *d_part = nullptr, *d_S = nullptr;
     double* h_S = nullptr;                   // pinned copy of the scalars
+    // kCheckEvery CG iterations of each solve as one HIP graph (kernels only),
+    // captured on `cap` at the first field evaluation; replayed on the caller's stream
+    hipStream_t cap = nullptr;
+    hipGraphExec_t g_u1 = nullptr, g_u2 = nullptr;
+    bool graphs_tried = false;
 
     ~h2dlp_fem_ctx() {
         if (device < 0) return;
@@ -72,11 +79,15 @@ struct h2dlp_fem_ctx {
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(device);
         (void)hipDeviceSynchronize();
+        if (g_u1) (void)hipGraphExecDestroy(g_u1);
+        if (g_u2) (void)hipGraphExecDestroy(g_u2);
+        if (cap) (void)hipStreamDestroy(cap);
         for (void* p : bufs) (void)hipFree(p);
         if (h_S) (void)hipHostFree(h_S);
         if (bop) h2dlp_free(bop);
         (void)hipSetDevice(cur);
     }
+    std::vector<size_t> buf_bytes;
     template <typename T>
     T* alloc(size_t count) {
         void* p = nullptr;
@@ -86,8 +97,19 @@ struct h2dlp_fem_ctx {
             throw std::bad_alloc();
         }
         bufs.push_back(p);
+        buf_bytes.push_back(b);
         bytes += b;
         return static_cast<T*>(p);
+    }
+    void release(void* p) {
+        for (size_t q = 0; q < bufs.size(); ++q)
+            if (bufs[q] == p) {
+                (void)hipFree(p);
+                bytes -= buf_bytes[q];
+                bufs.erase(bufs.begin() + long(q));
+                buf_bytes.erase(buf_bytes.begin() + long(q));
+                return;
+            }
     }
     template <typename T>
     T* upload(const std::vector<T>& v, hipStream_t st) {
@@ -99,8 +121,8 @@ struct h2dlp_fem_ctx {
         return d;
     }
     FemCg cg(const double* dinv) const {
-        return FemCg{n, d_rowptr, d_col, d_val, dinv, d_r, d_z, d_p, d_q, d_part, d_part + kFemBlocks,
-                     d_part + 2 * kFemBlocks, d_S};
+        return FemCg{n, d_ell_off, d_ell_w, d_ell_col, d_ell_val, dinv, d_r, d_z, d_p, d_q, d_part,
+                     d_part + kSpmvBlocks, d_part + kSpmvBlocks + kFemBlocks, d_S};
     }
 };
 
@@ -210,6 +232,26 @@ int fem_build_impl(h2dlp_fem_ctx* f, const h2dlp_volume* vol, const h2dlp_option
         rowptr[i + 1] = int64_t(col.size());
     }
     f->nnz = int64_t(col.size());
+    // sliced ELL: slices of kSlice rows, each as wide as its longest row
+    const int64_t n_slices = (n + kSlice - 1) / kSlice;
+    std::vector<int64_t> ell_off(size_t(n_slices) + 1, 0);
+    std::vector<int32_t> ell_w(size_t(n_slices), 0);
+    for (int64_t sl = 0; sl < n_slices; ++sl) {
+        int64_t w = 0;
+        for (int64_t i = sl * kSlice; i < std::min(n, (sl + 1) * kSlice); ++i) w = std::max(w, rowptr[i + 1] - rowptr[i]);
+        ell_w[sl] = int32_t(w);
+        ell_off[sl + 1] = ell_off[sl] + w * kSlice;
+    }
+    std::vector<int32_t> ell_col(static_cast<size_t>(ell_off[n_slices]));
+    for (int64_t sl = 0; sl < n_slices; ++sl)
+        for (int64_t r = 0; r < kSlice; ++r) {
+            const int64_t i = std::min(sl * kSlice + r, n - 1);      // rows past n repeat the last one
+            for (int64_t k = 0; k < ell_w[sl]; ++k) {
+                const int64_t e = rowptr[i] + k;
+                ell_col[size_t(ell_off[sl] + kSlice * k + r)] = e < rowptr[i + 1] ? col[size_t(e)] : int32_t(i);
+            }
+        }
+    f->ell_entries = ell_off[n_slices];
     std::vector<uint8_t> on_b(size_t(n), 0);
     for (int32_t v : f->bnodes) on_b[v] = 1;
     // device: geometry, stiffness, diagonals
@@ -220,22 +262,26 @@ int fem_build_impl(h2dlp_fem_ctx* f, const h2dlp_volume* vol, const h2dlp_option
     f->d_geo = f->alloc<double>(size_t(kGeo) * size_t(T));
     f->d_inc_off = f->upload(inc_off, st);
     f->d_inc = f->upload(inc, st);
-    f->d_rowptr = f->upload(rowptr, st);
-    f->d_col = f->upload(col, st);
-    f->d_val = f->alloc<double>(col.size());
+    int64_t* d_rowptr = f->upload(rowptr, st);
+    int32_t* d_col = f->upload(col, st);
+    double* d_val = f->alloc<double>(col.size());
+    f->d_ell_off = f->upload(ell_off, st);
+    f->d_ell_w = f->upload(ell_w, st);
+    f->d_ell_col = f->upload(ell_col, st);
+    f->d_ell_val = f->alloc<double>(ell_col.size());
     f->d_dinv_free = f->alloc<double>(size_t(n));
     f->d_dinv_fix = f->alloc<double>(size_t(n));
     uint8_t* d_onb = f->upload(on_b, st);
     f->d_bnode = f->upload(f->bnodes, st);
     hcheck(fem_geometry(T, d_xyz, f->d_tet, f->d_geo, st), "element geometry");
-    hcheck(fem_stiffness(n, f->d_inc_off, f->d_inc, f->d_tet, f->d_geo, f->d_rowptr, f->d_col, f->d_val, st),
-           "stiffness");
-    hcheck(fem_dinv(n, f->d_rowptr, f->d_col, f->d_val, d_onb, f->d_dinv_free, f->d_dinv_fix, st), "diagonal");
+    hcheck(fem_stiffness(n, f->d_inc_off, f->d_inc, f->d_tet, f->d_geo, d_rowptr, d_col, d_val, st), "stiffness");
+    hcheck(fem_dinv(n, d_rowptr, d_col, d_val, d_onb, f->d_dinv_free, f->d_dinv_fix, st), "diagonal");
+    hcheck(fem_to_ell(n, d_rowptr, d_val, f->cg(f->d_dinv_free), f->d_ell_val, st), "sliced ELL");
     for (double** v : {&f->d_b, &f->d_r, &f->d_z, &f->d_p, &f->d_q, &f->d_ones, &f->d_u1, &f->d_u2, &f->d_g})
         *v = f->alloc<double>(size_t(n));
     f->d_ub1 = f->alloc<double>(f->bnodes.size());
     f->d_ub2 = f->alloc<double>(f->bnodes.size());
-    f->d_part = f->alloc<double>(3 * size_t(kFemBlocks));
+    f->d_part = f->alloc<double>(size_t(kSpmvBlocks) + 2 * size_t(kFemBlocks));
     f->d_S = f->alloc<double>(kSlots);
     std::vector<double> ones(size_t(n), 1.0);
     hcheck(hipMemcpyAsync(f->d_ones, ones.data(), sizeof(double) * size_t(n), hipMemcpyHostToDevice, st), "upload");
@@ -244,20 +290,43 @@ int fem_build_impl(h2dlp_fem_ctx* f, const h2dlp_volume* vol, const h2dlp_option
         throw std::bad_alloc();
     }
     hcheck(hipStreamSynchronize(st), "build");
-    // build-only arrays
-    for (void* p : {static_cast<void*>(d_xyz), static_cast<void*>(d_onb)}) {
-        auto it = std::find(f->bufs.begin(), f->bufs.end(), p);
-        (void)hipFree(p);
-        f->bufs.erase(it);
-    }
-    f->bytes -= sizeof(double) * size_t(3 * n) + std::max<size_t>(size_t(n), 1);
+    // build-only arrays: coordinates, boundary flags and the CSR form
+    for (void* p : {static_cast<void*>(d_xyz), static_cast<void*>(d_onb), static_cast<void*>(d_rowptr),
+                    static_cast<void*>(d_col), static_cast<void*>(d_val)})
+        f->release(p);
     return H2DLP_OK;
 }
 
+// kCheckEvery CG iterations (an even count, so the r.z slots alternate the
+// same way in every block of them) captured as one graph of kernels; NULL
+// when capture is not available (the iterations are then launched one by one)
+hipGraphExec_t capture_steps(h2dlp_fem_ctx* f, const FemCg& c, double* x) {
+    static_assert(kCheckEvery % 2 == 0, "the r.z slot parity repeats every two iterations");
+    if (!f->cap && hipStreamCreateWithFlags(&f->cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        f->cap = nullptr;
+        return nullptr;
+    }
+    if (hipStreamBeginCapture(f->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    bool ok = true;
+    for (int q = 0; q < kCheckEvery; ++q) ok = ok && fem_cg_step(c, x, q, f->cap) == hipSuccess;
+    hipGraph_t g = nullptr;
+    ok = hipStreamEndCapture(f->cap, &g) == hipSuccess && ok;
+    hipGraphExec_t e = nullptr;
+    if (ok && g && hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) e = nullptr;
+    if (g) (void)hipGraphDestroy(g);
+    if (!e) (void)hipGetLastError();
+    return e;
+}
+
 // Jacobi-preconditioned CG from zero on the rows with dinv != 0; returns the
-// iterations and the relative residual |r| / |r0|
+// iterations and the relative residual |r| / |r0|.  `graph`: kCheckEvery
+// iterations of this solve as one graph, or NULL.
 int cg_solve(h2dlp_fem_ctx* f, const FemCg& c, const double* b, double* x, double tol, int max_iter, hipStream_t st,
-             int* iters, double* rel) {
+             hipGraphExec_t graph, int* iters, double* rel) {
     hcheck(fem_cg_start(c, b, x, st), "cg");
     hcheck(hipMemcpyAsync(f->h_S, f->d_S, sizeof(double) * kSlots, hipMemcpyDeviceToHost, st), "cg");
     hcheck(hipStreamSynchronize(st), "cg");
@@ -268,7 +337,12 @@ int cg_solve(h2dlp_fem_ctx* f, const FemCg& c, const double* b, double* x, doubl
     int it = 0;
     while (it < max_iter) {
         const int steps = std::min(kCheckEvery, max_iter - it);
-        for (int q = 0; q < steps; ++q, ++it) hcheck(fem_cg_step(c, x, it, st), "cg");
+        if (graph && steps == kCheckEvery) {          // it is a multiple of kCheckEvery here
+            hcheck(hipGraphLaunch(graph, st), "cg graph");
+            it += steps;
+        } else {
+            for (int q = 0; q < steps; ++q, ++it) hcheck(fem_cg_step(c, x, it, st), "cg");
+        }
         hcheck(hipMemcpyAsync(f->h_S, f->d_S, sizeof(double) * kSlots, hipMemcpyDeviceToHost, st), "cg");
         hcheck(hipStreamSynchronize(st), "cg");
         *rel = std::sqrt(std::max(0.0, f->h_S[kSlotRR]) / rr0);
@@ -282,11 +356,17 @@ int fem_field_impl(h2dlp_fem_ctx* f, const double* m, double* h, double* u1_out,
                    int max_iter, hipStream_t st, h2dlp_fem_result* res) {
     const int64_t n = f->n;
     h2dlp_fem_result r{};
+    if (!f->graphs_tried) {
+        f->graphs_tried = true;
+        f->g_u1 = capture_steps(f, f->cg(f->d_dinv_free), f->d_u1);
+        f->g_u2 = capture_steps(f, f->cg(f->d_dinv_fix), f->d_u2);
+    }
     // u1: the Neumann problem, right side moved to zero sum, solution to zero node sum
     hcheck(fem_rhs(n, f->d_inc_off, f->d_inc, f->d_geo, m, f->d_b, st), "right side");
     hcheck(fem_dot(n, f->d_b, f->d_ones, f->d_part, f->d_S, kSlotMean, 1.0 / double(n), st), "mean");
     hcheck(fem_shift(n, f->d_b, f->d_S, kSlotMean, st), "mean");
-    int rc = cg_solve(f, f->cg(f->d_dinv_free), f->d_b, f->d_u1, tol, max_iter, st, &r.iters_u1, &r.resid_u1);
+    int rc = cg_solve(f, f->cg(f->d_dinv_free), f->d_b, f->d_u1, tol, max_iter, st, f->g_u1, &r.iters_u1,
+                      &r.resid_u1);
     if (rc != H2DLP_OK) return rc;
     hcheck(fem_dot(n, f->d_u1, f->d_ones, f->d_part, f->d_S, kSlotMean, 1.0 / double(n), st), "mean");
     hcheck(fem_shift(n, f->d_u1, f->d_S, kSlotMean, st), "mean");
@@ -300,7 +380,7 @@ int fem_field_impl(h2dlp_fem_ctx* f, const double* m, double* h, double* u1_out,
     const FemCg cd = f->cg(f->d_dinv_fix);
     hcheck(fem_spmv(cd, f->d_g, f->d_q, st), "Dirichlet right side");
     hcheck(fem_scale(n, -1.0, f->d_q, f->d_b, st), "Dirichlet right side");
-    rc = cg_solve(f, cd, f->d_b, f->d_u2, tol, max_iter, st, &r.iters_u2, &r.resid_u2);
+    rc = cg_solve(f, cd, f->d_b, f->d_u2, tol, max_iter, st, f->g_u2, &r.iters_u2, &r.resid_u2);
     if (rc != H2DLP_OK) return rc;
     hcheck(fem_axpy(n, f->d_u2, 1.0, f->d_g, f->d_u2, st), "u2");
     // H = -grad (u1 + u2) and the energy

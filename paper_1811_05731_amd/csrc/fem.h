@@ -9,7 +9,9 @@
 namespace h2dlp {
 
 constexpr int kGeo = 13;                   // doubles per tetrahedron: volume, then grad phi_0..3
-constexpr unsigned kFemBlocks = 1024;      // blocks of the reducing kernels (their partials)
+constexpr unsigned kFemBlocks = 1024;      // blocks of the reducing vector kernels (their partials)
+constexpr unsigned kSpmvBlocks = 2048;     // most blocks of the matrix-vector product (one row a thread)
+constexpr int kSlice = 64;                 // rows of a sliced-ELL slice (one wavefront)
 
 // slots of the device scalar array
 constexpr int kSlotRZ0 = 0;                // r . z of the current and of the next CG iteration (0, 1)
@@ -19,22 +21,30 @@ constexpr int kSlotMean = 4;               // a mean to remove
 constexpr int kSlotEnergy = 5;             // -(1/2) sum vol M . H
 constexpr int kSlots = 8;
 
-// One preconditioned CG solve on the stiffness matrix (CSR, FP64): rows with
-// dinv = 0 are fixed (their residual is held at zero).
+// One preconditioned CG solve on the stiffness matrix, FP64 in sliced ELL:
+// slice s (rows 64 s .. 64 s + 63) holds w[s] slots, entry (row 64 s + r,
+// slot k) at off[s] + 64 k + r, its columns in ascending order, padding with
+// the row's own column and 0.  Rows with dinv = 0 are fixed (their residual is
+// held at zero).
 struct FemCg {
     int64_t n;
-    const int64_t* rowptr;
+    const int64_t* off;
+    const int32_t* width;
     const int32_t* col;
     const double* val;
     const double* dinv;
     double *r, *z, *p, *q;
-    double *part_pq, *part_rz, *part_rr;   // kFemBlocks each
+    double *part_pq;                       // kSpmvBlocks (one per block of the matrix-vector product)
+    double *part_rz, *part_rr;             // kFemBlocks each
     double* S;                             // kSlots
 };
 
 hipError_t fem_geometry(int64_t n_tets, const double* xyz, const int32_t* tet, double* geo, hipStream_t st);
 hipError_t fem_stiffness(int64_t n, const int64_t* inc_off, const int32_t* inc, const int32_t* tet, const double* geo,
                          const int64_t* rowptr, const int32_t* col, double* val, hipStream_t st);
+// the CSR values into the sliced-ELL layout of `c` (its columns already set)
+hipError_t fem_to_ell(int64_t n, const int64_t* rowptr, const double* val, const FemCg& c, double* ell_val,
+                      hipStream_t st);
 hipError_t fem_dinv(int64_t n, const int64_t* rowptr, const int32_t* col, const double* val, const uint8_t* on_boundary,
                     double* dinv_free, double* dinv_fix, hipStream_t st);
 // out = s a

@@ -7,6 +7,8 @@
 // consumer sums in the same order, so results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fem.h"
 
 namespace h2dlp {
@@ -121,26 +123,42 @@ __global__ void __launch_bounds__(kT) k_rhs(int64_t n, const int64_t* __restrict
     b[i] = s;
 }
 
-// q = A p over 16 lanes a row (rows of P1 tetrahedral stiffness hold about 15
-// entries), with the block partial of p . q
-__global__ void __launch_bounds__(kT) k_spmv_dot(int64_t n, const int64_t* __restrict__ rowptr,
-                                                const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                const double* __restrict__ p, double* __restrict__ q,
-                                                double* __restrict__ part) {
+// q = A p, one thread per row over its slice's slots (all loads of a slot are
+// contiguous across the wavefront and independent of each other), with the
+// block partial of p . q
+__global__ void __launch_bounds__(kT) k_spmv_dot(int64_t n, const int64_t* __restrict__ off,
+                                                const int32_t* __restrict__ width, const int32_t* __restrict__ col,
+                                                const double* __restrict__ val, const double* __restrict__ p,
+                                                double* __restrict__ q, double* __restrict__ part) {
     __shared__ double sh[kT / 64 + 1];
-    const int lane = threadIdx.x & 15;
     double acc = 0.0;
-    for (int64_t i = (int64_t(blockIdx.x) * kT + threadIdx.x) >> 4; i < n; i += int64_t(gridDim.x) * (kT / 16)) {
-        double s = 0.0;
-        for (int64_t k = rowptr[i] + lane; k < rowptr[i + 1]; k += 16) s += val[k] * p[col[k]];
-        for (int o = 8; o > 0; o >>= 1) s += __shfl_xor(s, o, 16);
-        if (lane == 0) {
+    for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i - threadIdx.x < n; i += int64_t(gridDim.x) * kT) {
+        if (i < n) {
+            const int64_t sl = i / kSlice;
+            const int64_t base = off[sl] + (i - sl * kSlice);
+            const int w = width[sl];
+            double s = 0.0;
+#pragma unroll 4
+            for (int k = 0; k < w; ++k) s += val[base + int64_t(kSlice) * k] * p[col[base + int64_t(kSlice) * k]];
             q[i] = s;
             acc += p[i] * s;
         }
     }
     const double t = block_sum(acc, sh);
     if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// ELL values from the CSR ones (row i's k-th entry into slot k; the rest of
+// the row's slots hold 0 at its own column)
+__global__ void __launch_bounds__(kT) k_to_ell(int64_t n, const int64_t* __restrict__ rowptr,
+                                              const double* __restrict__ val, const int64_t* __restrict__ off,
+                                              const int32_t* __restrict__ width, double* __restrict__ ell) {
+    const int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x;
+    if (i >= n) return;
+    const int64_t sl = i / kSlice;
+    const int64_t base = off[sl] + (i - sl * kSlice);
+    const int64_t r0 = rowptr[i], len = rowptr[i + 1] - r0;
+    for (int k = 0; k < width[sl]; ++k) ell[base + int64_t(kSlice) * k] = k < len ? val[r0 + k] : 0.0;
 }
 
 // partials of a . b
@@ -191,8 +209,9 @@ __global__ void __launch_bounds__(kT) k_cg_start(int64_t n, const double* __rest
     if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
 }
 
-// alpha = rz / (p . q) from the partials; x += alpha p, r -= alpha q (zero
-// where fixed), z = dinv r; partials of the new r . z and r . r
+// alpha = rz / (p . q) from the matrix-vector product's partials; x += alpha
+// p, r -= alpha q (zero where fixed), z = dinv r; partials of the new r . z
+// and r . r
 __global__ void __launch_bounds__(kT) k_cg_update(int64_t n, int nb, const double* __restrict__ part_pq,
                                                  const double* __restrict__ S, int rz_slot,
                                                  const double* __restrict__ dinv, double* __restrict__ x,
@@ -338,6 +357,12 @@ hipError_t fem_scale(int64_t n, double s, const double* a, double* out, hipStrea
     return hipGetLastError();
 }
 
+hipError_t fem_to_ell(int64_t n, const int64_t* rowptr, const double* val, const FemCg& c, double* ell_val,
+                      hipStream_t st) {
+    if (n > 0) hipLaunchKernelGGL(k_to_ell, dim3(blocks_of(n)), dim3(kT), 0, st, n, rowptr, val, c.off, c.width, ell_val);
+    return hipGetLastError();
+}
+
 hipError_t fem_rhs(int64_t n, const int64_t* inc_off, const int32_t* inc, const double* geo, const double* m,
                    double* b, hipStream_t st) {
     if (n > 0) hipLaunchKernelGGL(k_rhs, dim3(blocks_of(n)), dim3(kT), 0, st, n, inc_off, inc, geo, m, b);
@@ -364,19 +389,25 @@ hipError_t fem_cg_start(const FemCg& c, const double* b, double* x, hipStream_t 
     return hipGetLastError();
 }
 
+unsigned spmv_blocks(int64_t n) {
+    return unsigned(std::max<int64_t>(1, std::min<int64_t>((n + kT - 1) / kT, kSpmvBlocks)));
+}
+
 hipError_t fem_cg_step(const FemCg& c, double* x, int iter, hipStream_t st) {
     const int rz_old = kSlotRZ0 + (iter & 1), rz_new = kSlotRZ0 + ((iter + 1) & 1);
-    hipLaunchKernelGGL(k_spmv_dot, dim3(kFemBlocks), dim3(kT), 0, st, c.n, c.rowptr, c.col, c.val, c.p, c.q,
+    const unsigned nb = spmv_blocks(c.n);
+    hipLaunchKernelGGL(k_spmv_dot, dim3(nb), dim3(kT), 0, st, c.n, c.off, c.width, c.col, c.val, c.p, c.q,
                        c.part_pq);
-    hipLaunchKernelGGL(k_cg_update, dim3(kFemBlocks), dim3(kT), 0, st, c.n, int(kFemBlocks), c.part_pq, c.S, rz_old,
-                       c.dinv, x, c.r, c.z, c.p, c.q, c.part_rz, c.part_rr);
+    hipLaunchKernelGGL(k_cg_update, dim3(kFemBlocks), dim3(kT), 0, st, c.n, int(nb), c.part_pq, c.S, rz_old, c.dinv,
+                       x, c.r, c.z, c.p, c.q, c.part_rz, c.part_rr);
     hipLaunchKernelGGL(k_cg_direction, dim3(kFemBlocks), dim3(kT), 0, st, c.n, int(kFemBlocks), c.part_rz, c.part_rr,
                        c.S, rz_old, rz_new, c.z, c.p);
     return hipGetLastError();
 }
 
 hipError_t fem_spmv(const FemCg& c, const double* x, double* y, hipStream_t st) {
-    hipLaunchKernelGGL(k_spmv_dot, dim3(kFemBlocks), dim3(kT), 0, st, c.n, c.rowptr, c.col, c.val, x, y, c.part_pq);
+    hipLaunchKernelGGL(k_spmv_dot, dim3(spmv_blocks(c.n)), dim3(kT), 0, st, c.n, c.off, c.width, c.col, c.val, x, y,
+                       c.part_pq);
     return hipGetLastError();
 }
 

@@ -117,3 +117,22 @@ def test_field_arguments_are_checked(lib):
     r = f.field(m, h)                                     # zero magnetisation: zero field
     assert r.energy == 0.0 and float(h.abs().max()) == 0.0
     f.close()
+
+
+def test_repeated_evaluations_are_identical(lib):
+    # the CG iterations between two residual reads replay one captured graph;
+    # every call, and calls with other magnetisations in between, give the
+    # same bits
+    xyz, tets = MESHES["box"]()
+    f = lib.FemField(xyz, tets, order=4, leaf=32, eta=2.0, precision="fp64")
+    m1 = torch.tensor(volume.vortex_m(xyz, tets, core=0.3, seed=1), device="cuda")
+    m2 = torch.tensor(volume.uniform_m(len(tets), (1, 0, 0)), device="cuda")
+    outs = []
+    for m in (m1, m2, m1, m1):
+        h = torch.empty_like(m)
+        r = f.field(m, h, tol=TOL)
+        outs.append((h.cpu().numpy(), r.energy, r.iters_u1, r.iters_u2))
+    f.close()
+    for a in (outs[2], outs[3]):
+        assert np.array_equal(a[0], outs[0][0]) and a[1:] == outs[0][1:]
+    assert not np.array_equal(outs[1][0], outs[0][0])
