@@ -247,7 +247,18 @@ class Server:
     # -- registration and memory ----------------------------------------------------
     def add_mesh(self, spec: MeshSpec):
         resident, ws = self.backend.plan_bytes(spec)
-        self.meshes[spec.mesh_id] = _Mesh(spec, int(resident), int(ws))
+        m = _Mesh(spec, int(resident), int(ws))
+        self.meshes[spec.mesh_id] = m
+        built = getattr(self.backend, "built_bytes", None)
+        if spec.recompress_eps > 0 and built is not None:
+            # a recompressed operator's ranks are known only once built, and the
+            # plan's full-rank count can be many times its size: build it now for
+            # the exact size, and park it in host memory until it is admitted
+            m.op = self.backend.build(spec)
+            m.builds += 1
+            m.resident_bytes = int(built(m.op))
+            self.backend.offload(m.op)
+            m.offloads += 1
 
     def _max_values(self) -> int:
         return self.max_batch_rhs * max((m.spec.n_nodes for m in self.meshes.values()), default=1)
@@ -295,11 +306,6 @@ class Server:
         if m.op is None:
             m.op = self.backend.build(m.spec)
             m.builds += 1
-            # a recompressed operator's ranks are known only once built: the
-            # plan's count (full ranks) is an upper bound, the built one is exact
-            built = getattr(self.backend, "built_bytes", None)
-            if built is not None:
-                m.resident_bytes = min(m.resident_bytes, int(built(m.op)))
         else:
             self.backend.reload(m.op, slot)
             m.reloads += 1

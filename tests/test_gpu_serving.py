@@ -64,19 +64,22 @@ def test_async_reload_then_apply_on_another_stream(mods):
         assert np.array_equal(d2.cpu().numpy(), before)
 
 
-@pytest.mark.parametrize("coupling", ["stored", "generated"])
-def test_mix_equals_alone_under_budget(mods, coupling):
-    # generated coupling is the mode the benchmark serves
+@pytest.mark.parametrize("coupling,eps", [("stored", 0.0), ("generated", 0.0), ("stored", 1e-6)])
+def test_mix_equals_alone_under_budget(mods, coupling, eps):
+    # recompressed stored coupling is the mode the benchmark serves; a
+    # recompressed operator is built when registered, for its exact size
     h2dlp, serving = mods
     ms = _meshes()
-    specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32", coupling=coupling)
+    specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32", coupling=coupling, recompress_eps=eps)
              for k, (x, t) in ms.items()]
     backend = serving.GpuBackend(0)
-    sizes = {s.mesh_id: backend.plan_bytes(s) for s in specs}
-    res = sorted(r for r, _ in sizes.values())
     srv = serving.Server(backend, 0, n_slots=3, max_batch_rhs=24)
     for s in specs:
         srv.add_mesh(s)
+    res = sorted(m.resident_bytes for m in srv.meshes.values())
+    if eps:
+        for s in specs:
+            assert srv.meshes[s.mesh_id].resident_bytes < backend.plan_bytes(s)[0]
     srv.budget = srv.fixed_bytes() + res[-1] + res[-2] - 1     # never all three at once
     srv.prewarm()
     g = np.random.default_rng(4)
@@ -92,7 +95,8 @@ def test_mix_equals_alone_under_budget(mods, coupling):
     assert stats["served"] == 60, [r.error for r in reqs if r.error]
     assert sum(stats["offloads"].values()) > 0 and sum(stats["reloads"].values()) > 0
     assert stats["batches"] < 60
-    alone_ops = {s.mesh_id: h2dlp.Operator(s.xyz, s.tri, s.order, s.leaf, s.eta, s.precision, coupling=coupling)
+    alone_ops = {s.mesh_id: h2dlp.Operator(s.xyz, s.tri, s.order, s.leaf, s.eta, s.precision, coupling=coupling,
+                                           recompress_eps=eps)
                  for s in specs}
     for r in reqs:
         assert np.array_equal(r.result, _apply(alone_ops[r.mesh_id], r.u1)), r.rid
