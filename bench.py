@@ -670,10 +670,10 @@ def main():
     if rec_eps > 0 and args.dense_far_max < 0:
         dense_far_max = 0                          # the recompression replaces the exact small blocks
 
-    def build(prec, coupling, dmax=None, eps=0.0):
+    def build(prec, coupling, dmax=None, eps=0.0, row_basis="stored"):
         return h2dlp.Operator(xyz, tri, order=case.order, leaf=case.leaf, eta=case.eta, precision=prec, device=0,
                               coupling=coupling, dense_far_max=dmax_of(coupling) if dmax is None else dmax,
-                              recompress_eps=eps)
+                              recompress_eps=eps, row_basis=row_basis)
 
     t0 = time.perf_counter()
     op = build(args.precision, args.coupling, dense_far_max, rec_eps)
@@ -746,29 +746,32 @@ def main():
         print("# other precisions and representations", file=sys.stderr, flush=True)
         variants, outs = {}, {}
         # each in the benchmark's configuration of its coupling mode, and the
-        # plain interpolation H2 matrix (no exact admissible blocks)
+        # plain interpolation H2 matrix (no exact admissible blocks); the last
+        # two regenerate the leaf row bases in the apply
         configs = [("fp64", "stored", None, 0.0), ("fp64", "generated", None, 0.0), ("fp32", "stored", None, 0.0),
                    ("fp32", "generated", None, 0.0), ("bf16x3", "stored", None, 0.0), ("bf16x6", "stored", None, 0.0),
                    ("fp64", "generated", 0, 0.0), ("fp32", "generated", 0, 0.0), ("bf16x3", "stored", 0, 0.0),
                    ("fp64", "stored", 0, 1e-6), ("fp32", "stored", 0, 1e-6)]
-        for prec, cpl, dm, eps in configs:
+        configs = [c + ("stored",) for c in configs] + [("fp32", "generated", None, 0.0, "generated"),
+                                                        ("fp32", "generated", 0, 0.0, "generated")]
+        for prec, cpl, dm, eps, rb in configs:
             dmax = dmax_of(cpl) if dm is None else dm
-            if (prec, cpl, dmax, eps) == (args.precision, args.coupling, dense_far_max, rec_eps):
+            if (prec, cpl, dmax, eps, rb) == (args.precision, args.coupling, dense_far_max, rec_eps, "stored"):
                 continue
             if (prec.startswith("bf16") or cpl == "generated" or eps > 0) and case.order > 5:
                 continue
             t0 = time.perf_counter()
-            opv = build(prec, cpl, dmax, eps)
+            opv = build(prec, cpl, dmax, eps, rb)
             torch.cuda.synchronize()
             bs = time.perf_counter() - t0
             msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=("coupling",))
             key = ((prec if cpl == "stored" else f"{prec}_generated") + ("_plain" if dm == 0 and dmax == 0 and not eps
                                                                         else "")
-                   + ("_recompressed" if eps else ""))
+                   + ("_recompressed" if eps else "") + ("_regenerated_v" if rb == "generated" else ""))
             outs[key] = d_u2.cpu().numpy()
             ev = 8 if prec == "fp64" else 4
             variants[key] = {"value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
-                             "dense_far_max": dmax, "recompress_eps": eps, "build_s": round(bs, 2),
+                             "dense_far_max": dmax, "recompress_eps": eps, "row_basis": rb, "build_s": round(bs, 2),
                              "coupling": roofline_of(opv.stats, prec, cpl, kv, n),
                              "resident_GB": round(opv.stats.bytes_resident / 1e9, 2),
                              "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9

@@ -86,7 +86,13 @@ typedef struct {
  * recompress_eps times the cluster's largest singular value, and every
  * coupling matrix is projected onto them and stored (r_t x r_s).  FP64 and
  * FP32, stored coupling, order <= 5 (else ENOTSUP).  h2dlp_plan reports the
- * interpolation sizes (an upper bound); the ranks are known after the build. */
+ * interpolation sizes (an upper bound); the ranks are known after the build.
+ * row_basis: H2DLP_ROW_BASIS_STORED keeps every leaf row basis V_t (n_t x k
+ * values, Section 4: V_t(i, nu) is the nu-th Lagrange polynomial of the leaf
+ * box's Chebyshev points at node xi_i).  H2DLP_ROW_BASIS_GENERATED keeps only
+ * the node coordinates (24 bytes a node instead of k values) and evaluates
+ * V_t inside the apply: the same operator without the row-basis bytes.
+ * Interpolation bases only (recompress_eps 0, else ENOTSUP). */
 typedef struct {
     int    order;
     int    leaf;
@@ -98,10 +104,14 @@ typedef struct {
     int    coupling;
     int64_t dense_far_max;
     double recompress_eps;
+    int    row_basis;
 } h2dlp_options;
 
 #define H2DLP_COUPLING_STORED     0
 #define H2DLP_COUPLING_GENERATED  1
+
+#define H2DLP_ROW_BASIS_STORED     0
+#define H2DLP_ROW_BASIS_GENERATED  1
 
 typedef struct h2dlp_ctx* h2dlp_handle;
 
@@ -127,7 +137,8 @@ typedef struct {
 } h2dlp_stats;
 
 /* Fill *opt with defaults: order 4, leaf 32, eta 2, FP64, alpha 0.1, device -1,
- * stream NULL, coupling STORED, dense_far_max 0, recompress_eps 0. */
+ * stream NULL, coupling STORED, dense_far_max 0, recompress_eps 0, row_basis
+ * STORED. */
 void h2dlp_default_options(h2dlp_options* opt);
 
 /* Build the H2 operator for `mesh` (copied; the caller may free it on return).

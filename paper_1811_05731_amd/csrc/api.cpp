@@ -130,6 +130,12 @@ struct h2dlp_ctx {
     BlkDesc* d_blks_leaf = nullptr;
     ItemDesc* d_items_near = nullptr;   // the leaf items without their V_t block
     ItemDesc* d_items_v = nullptr;      // the leaf items' V_t block alone
+    // row basis regenerated in the apply: the leaves and the node coordinates
+    // (cluster order, N x 3)
+    bool regen_v = false;
+    std::vector<VLeaf> vgen;
+    VLeaf* d_vgen = nullptr;
+    double* d_vxyz = nullptr;
     int64_t* d_ns_off = nullptr;
     int32_t* d_ns_pos = nullptr;
     double* d_ns_val = nullptr;
@@ -239,7 +245,7 @@ struct h2dlp_ctx {
                 {(void**)&d_ns_val, false}, {(void**)&d_pool_up, false}, {(void**)&d_pool_down, false},
                 {(void**)&d_pool_q, false}, {(void**)&d_items_up, false}, {(void**)&d_blks_up, false},
                 {(void**)&d_items_down, false}, {(void**)&d_blks_down, false}, {(void**)&d_blks_v, false},
-                {(void**)&d_items_cpl_b, false},
+                {(void**)&d_items_cpl_b, false}, {(void**)&d_vgen, false}, {(void**)&d_vxyz, false},
                 {(void**)&d_ws, true}};
     }
     size_t bytes_of(void* p) const {
@@ -295,6 +301,9 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     const bool fp64 = h->prec == H2DLP_FP64;
     const bool rec = o->recompress_eps > 0.0;
     h->rec = rec;
+    const bool regen = o->row_basis == H2DLP_ROW_BASIS_GENERATED;
+    h->regen_v = regen;
+    const bool has_v = !rec && !regen;     // a leaf item's first block is V_t
 
     std::string err = build_structure(h->S, mesh->xyz, mesh->n_nodes, mesh->tri, mesh->n_tris, o->leaf, o->eta,
                                       o->alpha, !fp64);
@@ -413,11 +422,16 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
         std::sort(lst.begin(), lst.end(), [&](int32_t a, int32_t b) { return S.cl[a].begin < S.cl[b].begin; });
         const int32_t b0 = int32_t(h->blks_leaf.size());
         h->items_leaf.push_back(ItemDesc{int32_t(X.begin), int32_t(X.size()), b0,
-                                         int32_t(b0 + (rec ? 0 : 1) + lst.size())});
+                                         int32_t(b0 + (has_v ? 1 : 0) + lst.size())});
         if (rec) {           // V_t in FP64 for the recompression only, in a pool of the build
             off_v = align_block(off_v);
             h->vleaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), h->gid_of_pre[t], 0, off_v};
             off_v += int64_t(X.size()) * k;
+        } else if (regen) {  // V_t evaluated in the apply from the leaf's box
+            const int32_t g = h->gid_of_pre[t];
+            VLeaf v{int32_t(X.begin), int32_t(X.size()), g * k, 0, {}};
+            for (int a = 0; a < 6; ++a) v.box[a] = h->boxes[6 * size_t(g) + a];
+            h->vgen.push_back(v);
         } else {
             off_l = align_block(off_l);
             h->vleaves[q] = LeafDesc{int32_t(X.begin), int32_t(X.size()), h->gid_of_pre[t], 0, off_l};
@@ -437,8 +451,8 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     h->n_items_cpl = int32_t(h->items_cpl.size());
     h->n_items_leaf = int32_t(h->items_leaf.size());
     for (const ItemDesc& d : h->items_leaf) {     // block 0 of a leaf item is V_t, the rest near blocks
-        h->items_near.push_back(ItemDesc{d.out_row, d.m, d.blk_begin + (rec ? 0 : 1), d.blk_end});
-        if (!rec) h->items_v.push_back(ItemDesc{d.out_row, d.m, d.blk_begin, d.blk_begin + 1});
+        h->items_near.push_back(ItemDesc{d.out_row, d.m, d.blk_begin + (has_v ? 1 : 0), d.blk_end});
+        if (has_v) h->items_v.push_back(ItemDesc{d.out_row, d.m, d.blk_begin, d.blk_begin + 1});
     }
     // near-field items in node (depth-first) order rather than level order:
     // neighbouring items, dealt to one XCD in chunks, are then neighbouring
@@ -490,14 +504,16 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     }
     st.bytes_near = int64_t(e * size_t(near_entries));
     if (!fp64) st.bytes_near += int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8));
-    st.bytes_bases = int64_t(e * size_t(2 * N * int64_t(k)));
+    // a regenerated row basis keeps the node coordinates and the leaf boxes
+    const int64_t regen_bytes = regen ? int64_t(24 * N + int64_t(sizeof(VLeaf)) * h->n_leaves) : 0;
+    st.bytes_bases = int64_t(e * size_t((regen ? 1 : 2) * N * int64_t(k))) + regen_bytes;
     st.bytes_transfer = int64_t(e * size_t(C) * 3 * m * m);
     st.bytes_other = int64_t(N * 8 + 3 * int64_t(C) * 4 + N * 8 + int64_t(h->cgeo.size()) * 8 +
                              (h->items_fwd.size() + h->items_cpl.size() + h->items_leaf.size()) * sizeof(ItemDesc) +
                              (h->blks_fwd.size() + h->blks_cpl.size() + h->blks_leaf.size()) * sizeof(BlkDesc));
     st.workspace_bytes = int64_t(h->ws_bytes);
     st.bytes_resident = int64_t(e * size_t(off_wt + off_l) + h->elem_s * size_t(off_s)) + st.bytes_transfer +
-                        st.bytes_other +
+                        st.bytes_other + regen_bytes +
                         st.workspace_bytes + (fp64 ? 0 : int64_t((N + 1) * 8 + S.ring_pos.size() * (4 + 8)));
     const double h2_bytes = double(st.bytes_coupling + st.bytes_near + st.bytes_bases + st.bytes_transfer);
     st.compression = 1.0 - h2_bytes / (8.0 * double(N) * double(N));
@@ -789,6 +805,13 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     }
     h->d_pool_leaf = h->alloc<void>(e * size_t(h->off_l), &kept);
     if (!h->cgeo.empty()) h->d_cgeo = h->upload(h->cgeo, &kept, stream);
+    if (h->regen_v) {
+        std::vector<double> pxyz(3 * size_t(N));
+        for (int64_t p = 0; p < N; ++p)
+            for (int a = 0; a < 3; ++a) pxyz[3 * size_t(p) + a] = S.xyz[3 * size_t(S.perm[p]) + a];
+        h->d_vgen = h->upload(h->vgen, &kept, stream);
+        h->d_vxyz = h->upload(pxyz, &kept, stream);
+    }
     h->d_items_leaf = h->upload(h->items_leaf, &kept, stream);
     h->d_blks_leaf = h->upload(h->blks_leaf, &kept, stream);
     h->d_items_near = h->upload(h->items_near, &kept, stream);
@@ -830,8 +853,10 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     } else {
         check(launch_build_wt(dm, d_boxes, m, d_quad, int(quad.size() / 3), d_leaves, int64_t(h->leaves.size()),
                               h->prec, h->d_pool_wt, stream), "column basis");
-        check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf, stream),
-              "row basis");
+        if (!h->regen_v)
+            check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf,
+                                 stream),
+                  "row basis");
         check(launch_build_transfer(d_boxes, h->d_parent, C, m, h->prec, h->d_e, stream), "transfer");
     }
     if (h->d_cgeo == nullptr && !rec)
@@ -871,7 +896,7 @@ int pick_device(int* dev) {
 // a scratch buffer by its size only.  Loading plans the mesh again (the host
 // structure is deterministic) and takes the device buffers from the file.
 constexpr char kFileMagic[8] = {'H', '2', 'D', 'L', 'P', 'O', 'P', 'S'};
-constexpr uint32_t kFileFormat = 1;
+constexpr uint32_t kFileFormat = 2;
 constexpr size_t kStage = size_t(64) << 20;     // bytes per copy through pinned host memory
 
 struct FileOut {
@@ -1112,7 +1137,10 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
                                    : ProductArgs{h->d_items_v, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf,
                                                  h->d_pool_leaf, x, yh, nullptr};
         rec_begin(h, s, 5, &ev);
-        check(launch_product_add64(leafv, y64, prec, s), "leaf output");
+        if (h->regen_v)
+            check(launch_leaf_regen(h->d_vgen, h->n_leaves, h->d_vxyz, m, yh, y64, prec, s), "leaf output");
+        else
+            check(launch_product_add64(leafv, y64, prec, s), "leaf output");
         check(launch_unpermute(y64, io, N, nr, h->d_iperm, u2p, s), "unpermute");
         rec_end(h, s, 5, ev);
     }
@@ -1135,6 +1163,7 @@ void h2dlp_default_options(h2dlp_options* o) {
     o->coupling = H2DLP_COUPLING_STORED;
     o->dense_far_max = 0;
     o->recompress_eps = 0.0;
+    o->row_basis = H2DLP_ROW_BASIS_STORED;
 }
 
 static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_handle* out) {
@@ -1164,6 +1193,10 @@ static int check_args(const h2dlp_mesh* mesh, const h2dlp_options* o, h2dlp_hand
     if (o->recompress_eps > 0.0 && (o->order > 5 || o->coupling != H2DLP_COUPLING_STORED ||
                                     (o->precision != H2DLP_FP64 && o->precision != H2DLP_FP32)))
         return fail(H2DLP_ENOTSUP, "recompression needs FP64 or FP32, stored coupling and order <= 5");
+    if (o->row_basis != H2DLP_ROW_BASIS_STORED && o->row_basis != H2DLP_ROW_BASIS_GENERATED)
+        return fail(H2DLP_EINVAL, "unknown row basis mode");
+    if (o->row_basis == H2DLP_ROW_BASIS_GENERATED && o->recompress_eps > 0.0)
+        return fail(H2DLP_ENOTSUP, "a generated row basis needs the interpolation bases (recompress_eps 0)");
     return H2DLP_OK;
 }
 
@@ -1472,6 +1505,7 @@ int h2dlp_save(h2dlp_handle hh, const char* path) {
     const h2dlp_options& op = h->opt;
     o.pod(int32_t(op.order)); o.pod(int32_t(op.leaf)); o.pod(op.eta); o.pod(int32_t(op.precision));
     o.pod(op.alpha); o.pod(int32_t(op.coupling)); o.pod(op.dense_far_max); o.pod(op.recompress_eps);
+    o.pod(int32_t(op.row_basis));
     o.vec(h->S.xyz);
     o.vec(h->S.tri);
     derived_state<false>(o, h);
@@ -1534,6 +1568,7 @@ int h2dlp_load(const char* path, int device, h2dlp_handle* out) {
     o.order = in.pod<int32_t>(); o.leaf = in.pod<int32_t>(); o.eta = in.pod<double>();
     o.precision = in.pod<int32_t>(); o.alpha = in.pod<double>(); o.coupling = in.pod<int32_t>();
     o.dense_far_max = in.pod<int64_t>(); o.recompress_eps = in.pod<double>();
+    o.row_basis = in.pod<int32_t>();
     o.device = device;
     std::vector<double> xyz;
     std::vector<int32_t> tri;

@@ -22,7 +22,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
+#include "interp.h"
 #include "kernels.h"
 
 namespace h2dlp {
@@ -877,6 +879,80 @@ __global__ void __launch_bounds__(256) k_unpermute(const double* __restrict__ y6
         if (q < nr) u2[int64_t(q) * n + i] = IO(v[q]);
 }
 
+// Leaf output with the row basis regenerated: y64|_t += V_t yhat_t, where
+// V_t(i, nu) = Lx_a(x) Ly_b(y) Lz_c(z), nu = a + m b + m^2 c, is evaluated
+// here instead of read from memory (Section 4: the row factors are the
+// Lagrange polynomials of the leaf box's Chebyshev points at the collocation
+// nodes).  Each 1D value is w_l prod_{p != l} (x - p_p) with the barycentric
+// weight w_l = 1 / prod_{p != l} (p_l - p_p); the product of the three is
+// taken in FP64 and rounded once to T, as the stored basis is.  One wave per
+// leaf (at most 64 nodes), one lane per node with the 16 columns in
+// registers; the leaf's yhat (k x 16) is staged in LDS with coalesced loads
+// and every lane reads the same row of it (broadcast).
+template <typename T, int M>
+__global__ void __launch_bounds__(64) k_leaf_regen(const VLeaf* __restrict__ leaves, const double* __restrict__ xyz,
+                                                   const T* __restrict__ yh, double* __restrict__ y64) {
+    constexpr int K = M * M * M;
+    constexpr int VEC = 16 / int(sizeof(T));                 // values per 16-byte load
+    __shared__ double pts[3][M], wts[3][M];
+    __shared__ __attribute__((aligned(16))) T ys[K * RHS_TILE];
+    const VLeaf* L = leaves + blockIdx.x;
+    const int32_t pos = L->pos, n = L->n;
+    const int i = int(threadIdx.x);
+    {
+        using V4 = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+        const V4* src = reinterpret_cast<const V4*>(yh + int64_t(L->yrow) * RHS_TILE);
+        V4* dst = reinterpret_cast<V4*>(ys);
+        for (int q = i; q < K * RHS_TILE / VEC; q += 64) dst[q] = src[q];
+    }
+    if (i < 3 * M) pts[i / M][i % M] = cheb_point(L->box, i / M, M, i % M);
+    __syncthreads();
+    if (i < 3 * M) {
+        const int a = i / M, l = i % M;
+        double d = 1.0;
+        for (int p = 0; p < M; ++p)
+            if (p != l) d *= pts[a][l] - pts[a][p];
+        wts[a][l] = 1.0 / d;
+    }
+    __syncthreads();
+    if (i >= n) return;
+    const double* x = xyz + 3 * int64_t(pos + i);
+    double lx[M], ly[M];
+#pragma unroll
+    for (int l = 0; l < M; ++l) {
+        double vx = wts[0][l], vy = wts[1][l];
+#pragma unroll
+        for (int p = 0; p < M; ++p)
+            if (p != l) {
+                vx *= x[0] - pts[0][p];
+                vy *= x[1] - pts[1][p];
+            }
+        lx[l] = vx;
+        ly[l] = vy;
+    }
+    T acc[RHS_TILE];
+#pragma unroll
+    for (int r = 0; r < RHS_TILE; ++r) acc[r] = T(0);
+    for (int c = 0; c < M; ++c) {
+        double lz = wts[2][c];
+#pragma unroll
+        for (int p = 0; p < M; ++p)
+            if (p != c) lz *= x[2] - pts[2][p];
+#pragma unroll
+        for (int b = 0; b < M; ++b)
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                const T v = T(lx[a] * ly[b] * lz);
+                const T* yr = ys + RHS_TILE * (a + M * b + M * M * c);
+#pragma unroll
+                for (int r = 0; r < RHS_TILE; ++r) acc[r] = fma(v, yr[r], acc[r]);
+            }
+    }
+    double* out = y64 + int64_t(pos + i) * RHS_TILE;
+#pragma unroll
+    for (int r = 0; r < RHS_TILE; ++r) out[r] += double(acc[r]);
+}
+
 // One mode product of the Kronecker transfer E = Ex (x) Ey (x) Ez on a k x QC
 // slab in LDS (index nu = lx + m ly + m^2 lz, columns innermost), one thread
 // per line of M values along the axis:
@@ -1118,6 +1194,32 @@ hipError_t launch_unpermute(const double* y64, int io, int64_t n_nodes, int nr, 
         hipLaunchKernelGGL((k_unpermute<double>), dim3(grid), dim3(256), 0, st, y64, n_nodes, nr, iperm,
                            static_cast<double*>(u2));
     return hipGetLastError();
+}
+
+namespace {
+template <typename T>
+hipError_t leaf_regen_m(const VLeaf* leaves, unsigned n, const double* xyz, int m, const void* yh, double* y64,
+                        hipStream_t st) {
+    const T* y = static_cast<const T*>(yh);
+    switch (m) {
+#define H2DLP_REGEN_CASE(M_)                                                                                  \
+    case M_:                                                                                                  \
+        hipLaunchKernelGGL((k_leaf_regen<T, M_>), dim3(n), dim3(64), 0, st, leaves, xyz, y, y64);             \
+        break;
+        H2DLP_REGEN_CASE(1) H2DLP_REGEN_CASE(2) H2DLP_REGEN_CASE(3) H2DLP_REGEN_CASE(4)
+        H2DLP_REGEN_CASE(5) H2DLP_REGEN_CASE(6) H2DLP_REGEN_CASE(7) H2DLP_REGEN_CASE(8)
+#undef H2DLP_REGEN_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_leaf_regen(const VLeaf* leaves, int64_t n_leaves, const double* xyz, int m, const void* yh,
+                             double* y64, int prec, hipStream_t st) {
+    if (n_leaves == 0) return hipSuccess;
+    if (prec == P_FP64) return leaf_regen_m<double>(leaves, unsigned(n_leaves), xyz, m, yh, y64, st);
+    return leaf_regen_m<float>(leaves, unsigned(n_leaves), xyz, m, yh, y64, st);
 }
 
 hipError_t launch_product_store(const ProductArgs& a, int prec, bool prefer_rows, hipStream_t st) {

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
+#include "interp.h"
 #include "kernels.h"
 
 namespace h2dlp {
@@ -70,11 +71,9 @@ __device__ double lindholm_weight(const double* x, const double r[3][3], int a) 
     return s[op] / (8.0 * kPi * (0.5 * two_a)) * (term1 + term2);
 }
 
-// First-kind Chebyshev points of one box axis: c + h cos((2l + 1) pi / (2m)).
+// the m Chebyshev points of one box axis
 __device__ inline void cheb_axis(const double* box, int axis, int m, double* pts) {
-    const double lo = box[axis], hi = box[3 + axis];
-    const double c = 0.5 * (lo + hi), h = 0.5 * (hi - lo);
-    for (int l = 0; l < m; ++l) pts[l] = c + h * cos((2.0 * l + 1.0) * kPi / (2.0 * m));
+    for (int l = 0; l < m; ++l) pts[l] = cheb_point(box, axis, m, l);
 }
 
 __device__ inline double lagrange(const double* pts, int m, int l, double x) {

@@ -106,6 +106,19 @@ inline int coupling_cols(int k) {
     const int rt = (k + 15) / 16;
     return (rt <= 8 && (rt & (rt - 1)) == 0) ? 16 * rt : k;
 }
+// A leaf whose row basis the apply regenerates (interpolation bases only).
+struct VLeaf {
+    int32_t pos;        // first cluster position
+    int32_t n;          // nodes, at most 64
+    int32_t yrow;       // its first yhat row (level-order id times k)
+    int32_t pad;
+    double box[6];      // interpolation box: lo xyz, hi xyz
+};
+// y64 += V_t yhat_t for every leaf, V_t evaluated from xyz (node coordinates
+// in cluster order, N x 3) and the leaf's box; orders 1..8; yh in the operator
+// precision (FP64, else FP32)
+hipError_t launch_leaf_regen(const VLeaf* leaves, int64_t n_leaves, const double* xyz, int m, const void* yh,
+                             double* y64, int prec, hipStream_t st);
 hipError_t launch_upward(int32_t c_begin, int32_t c_end, const int32_t* child0, const int32_t* child1, const void* e,
                          void* xh, int m, int prec, hipStream_t st);
 hipError_t launch_downward(int32_t c_begin, int32_t c_end, const int32_t* parent, const void* e, void* yh, int m,

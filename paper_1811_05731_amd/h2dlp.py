@@ -24,6 +24,7 @@ NKINDS = 7
 KIND_NAMES = ("permute", "leaf_forward", "upward", "coupling", "downward", "leaf_output", "near_field")
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16x6": BF16X6}
 COUPLING = {"stored": 0, "generated": 1}        # H2DLP_COUPLING_STORED / _GENERATED
+ROW_BASIS = {"stored": 0, "generated": 1}       # H2DLP_ROW_BASIS_STORED / _GENERATED
 
 
 class H2dlpError(RuntimeError):
@@ -51,7 +52,7 @@ class _Options(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int), ("leaf", ctypes.c_int), ("eta", ctypes.c_double),
                 ("precision", ctypes.c_int), ("alpha", ctypes.c_double), ("device", ctypes.c_int),
                 ("stream", ctypes.c_void_p), ("coupling", ctypes.c_int), ("dense_far_max", ctypes.c_int64),
-                ("recompress_eps", ctypes.c_double)]
+                ("recompress_eps", ctypes.c_double), ("row_basis", ctypes.c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -198,7 +199,8 @@ class Operator:
 
     def __init__(self, xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0,
                  precision="fp64", alpha: float = 0.1, device: int = -1, stream=None, plan_only: bool = False,
-                 coupling: str = "stored", dense_far_max: int = 0, recompress_eps: float = 0.0):
+                 coupling: str = "stored", dense_far_max: int = 0, recompress_eps: float = 0.0,
+                 row_basis: str = "stored"):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         tri = np.ascontiguousarray(tri, dtype=np.int32)
         if xyz.ndim != 2 or xyz.shape[1] != 3 or tri.ndim != 2 or tri.shape[1] != 3:
@@ -213,6 +215,7 @@ class Operator:
         opt.coupling = COUPLING[coupling]
         opt.dense_far_max = int(dense_far_max)
         opt.recompress_eps = float(recompress_eps)
+        opt.row_basis = ROW_BASIS[row_basis] if isinstance(row_basis, str) else int(row_basis)
         h = ctypes.c_void_p()
         entry = _lib.h2dlp_plan if plan_only else _lib.h2dlp_build_ex
         _check(entry(ctypes.byref(mesh), ctypes.byref(opt), ctypes.byref(h)))
@@ -380,7 +383,7 @@ class FemField:
 
     def __init__(self, xyz, tet, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64",
                  alpha: float = 0.1, device: int = -1, coupling: str = "stored", dense_far_max: int = 0,
-                 recompress_eps: float = 0.0):
+                 recompress_eps: float = 0.0, row_basis: str = "stored"):
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         tet = np.ascontiguousarray(tet, dtype=np.int32)
         if xyz.ndim != 2 or xyz.shape[1] != 3 or tet.ndim != 2 or tet.shape[1] != 4:
@@ -394,6 +397,7 @@ class FemField:
         opt.coupling = COUPLING[coupling]
         opt.dense_far_max = int(dense_far_max)
         opt.recompress_eps = float(recompress_eps)
+        opt.row_basis = ROW_BASIS[row_basis] if isinstance(row_basis, str) else int(row_basis)
         h = ctypes.c_void_p()
         _check(_lib.h2dlp_fem_build(ctypes.byref(vol), ctypes.byref(opt), ctypes.byref(h)))
         self._h = h
@@ -439,10 +443,10 @@ class FemField:
 
 
 def plan(xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0, precision="fp64", alpha: float = 0.1,
-         coupling: str = "stored", dense_far_max: int = 0, recompress_eps: float = 0.0):
+         coupling: str = "stored", dense_far_max: int = 0, recompress_eps: float = 0.0, row_basis: str = "stored"):
     """Host-only structure and byte counts (no GPU needed)."""
     return Operator(xyz, tri, order, leaf, eta, precision, alpha, plan_only=True, coupling=coupling,
-                    dense_far_max=dense_far_max, recompress_eps=recompress_eps)
+                    dense_far_max=dense_far_max, recompress_eps=recompress_eps, row_basis=row_basis)
 
 
 def last_error() -> str:

@@ -26,6 +26,7 @@ def test_every_declared_symbol_is_exported():
 def test_default_options():
     o = h2dlp.default_options()
     assert (o["order"], o["leaf"], o["eta"], o["precision"], o["alpha"], o["device"]) == (4, 32, 2.0, 0, 0.1, -1)
+    assert (o["coupling"], o["dense_far_max"], o["recompress_eps"], o["row_basis"]) == (0, 0, 0.0, 0)
 
 
 def _plan_rc(xyz, tri, **kw):
@@ -124,6 +125,15 @@ def test_plan_sizes():
     sg = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, precision="fp32", coupling="generated").stats
     assert sg.bytes_coupling == 0 and sg.coupling_entries == s.coupling_entries
     assert s32.bytes_resident - sg.bytes_resident == 4 * s.coupling_entries - 48 * s.n_clusters
+    # regenerated row bases: V (N k values) gives way to the node coordinates
+    # (24 bytes a node) and a 64-byte record per leaf, and each leaf item loses
+    # its V block descriptor (16 bytes); k = 64 leaves no padding to account for
+    sr = h2dlp.plan(xyz, tri, order=4, leaf=32, eta=2.0, precision="fp32", row_basis="generated").stats
+    n = xyz.shape[0]
+    assert s32.bytes_bases - sr.bytes_bases == 4 * n * 64 - 24 * n - 64 * s.n_leaves
+    assert s32.bytes_resident - sr.bytes_resident == 4 * n * 64 - 24 * n - 48 * s.n_leaves
+    assert (sr.n_far, sr.n_near, sr.coupling_entries, sr.bytes_near) == (s32.n_far, s32.n_near,
+                                                                         s32.coupling_entries, s32.bytes_near)
     r, w = h2dlp.plan(xyz, tri).bytes()
     assert w > 0 and r > w
 
@@ -188,6 +198,9 @@ def test_recompression_arguments():
     assert _plan_rc(xyz, tri, recompress_eps=1e-6, coupling="generated") == h2dlp.ENOTSUP
     assert _plan_rc(xyz, tri, recompress_eps=1e-6, precision="bf16x3") == h2dlp.ENOTSUP
     assert _plan_rc(xyz, tri, order=6, recompress_eps=1e-6) == h2dlp.ENOTSUP
+    assert _plan_rc(xyz, tri, row_basis=2) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, row_basis=-1) == h2dlp.EINVAL
+    assert _plan_rc(xyz, tri, row_basis="generated", recompress_eps=1e-6) == h2dlp.ENOTSUP
     p = h2dlp.plan(xyz, tri, order=3, leaf=16, recompress_eps=1e-6, precision="fp32")
     q = h2dlp.plan(xyz, tri, order=3, leaf=16, precision="fp32")
     # before the build the plan reports the interpolation sizes, an upper bound
@@ -219,7 +232,7 @@ def test_persistence_errors(tmp_path):
     assert lib.h2dlp_load(str(other).encode(), -1, ctypes.byref(out)) == h2dlp.ENOTSUP
     # right header, cut short inside the options
     cut = tmp_path / "cut.op"
-    cut.write_bytes(b"H2DLPOPS" + (1).to_bytes(4, "little") + (34).to_bytes(4, "little")
+    cut.write_bytes(b"H2DLPOPS" + (2).to_bytes(4, "little") + (36).to_bytes(4, "little")
                     + ctypes.sizeof(h2dlp._Stats).to_bytes(4, "little") + bytes(10))
     assert lib.h2dlp_load(str(cut).encode(), -1, ctypes.byref(out)) == h2dlp.EINVAL
     assert out.value is None

@@ -130,11 +130,21 @@ def l8_rows(sphere_l8):
 
 @pytest.mark.parametrize("prec,coupling,dmax", L8_CONFIGS)
 def test_sphere_l8_against_oracle(lib, sphere_l8, l8_oracle, l8_rows, prec, coupling, dmax):
+    l8_check(lib, sphere_l8, l8_oracle, l8_rows, prec, coupling, dmax, "stored")
+
+
+@pytest.mark.parametrize("prec,coupling,dmax", [("fp64", "generated", 0), ("fp32", "generated", 7812)])
+def test_sphere_l8_regenerated_row_basis(lib, sphere_l8, l8_oracle, l8_rows, prec, coupling, dmax):
+    # V_t evaluated in the apply instead of read: the same operator, the same bounds
+    l8_check(lib, sphere_l8, l8_oracle, l8_rows, prec, coupling, dmax, "generated")
+
+
+def l8_check(lib, sphere_l8, l8_oracle, l8_rows, prec, coupling, dmax, row_basis):
     c, xyz, tri = sphere_l8
     H, u, ref_of = l8_oracle
     g, un = l8_rows
     op = lib.Operator(xyz, tri, order=c.order, leaf=c.leaf, eta=c.eta, precision=prec, coupling=coupling,
-                      dense_far_max=dmax)
+                      dense_far_max=dmax, row_basis=row_basis)
     assert op.stats.n_far_dense == H.with_dense_far_max(dmax).far_dense.shape[0]
     d_gpu = op.export_diagonal()
     # unit columns: all N rows
@@ -150,8 +160,8 @@ def test_sphere_l8_against_oracle(lib, sphere_l8, l8_oracle, l8_rows, prec, coup
     e_rows = relerr(out_rows, ref_rows)
     e_rows_k = relerr(out_rows - d_gpu[rows][None, :] * un[:, rows], k_rows)
     op.close()
-    print(f"L8 {prec} {coupling} dense_far_max={dmax}: unit columns {e_unit.max():.2e} (of K u: "
-          f"{e_unit_k.max():.2e}); N(0,1) rows {e_rows.max():.2e} (of K u: {e_rows_k.max():.2e})")
+    print(f"L8 {prec} {coupling} dense_far_max={dmax} row basis {row_basis}: unit columns {e_unit.max():.2e} "
+          f"(of K u: {e_unit_k.max():.2e}); N(0,1) rows {e_rows.max():.2e} (of K u: {e_rows_k.max():.2e})")
     assert np.all(e_unit_k <= K_BOUND[prec]), e_unit_k
     assert np.all(e_rows_k <= K_BOUND[prec]), e_rows_k
     check_target(prec, e_rows, f"L8 {coupling} dense_far_max={dmax}, N(0,1) input")

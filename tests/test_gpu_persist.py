@@ -30,6 +30,7 @@ def run(op, u, dtype=torch.float64):
 CONFIGS = [
     dict(precision="fp64"),
     dict(precision="fp32", coupling="generated", dense_far_max=2048),
+    dict(precision="fp32", coupling="generated", row_basis="generated"),
     dict(precision="bf16x3", dense_far_max=4096),
     dict(precision="fp32", recompress_eps=1e-6),
     dict(precision="fp64", recompress_eps=1e-4),
