@@ -142,6 +142,9 @@ struct h2dlp_ctx {
     void* d_ws = nullptr;
     size_t ws_bytes = 0, ws_x = 0, ws_x64 = 0, ws_y64 = 0, ws_xh = 0;
     int32_t n_items_fwd = 0, n_items_cpl = 0, n_items_leaf = 0;
+    // near-field items launched at the fork; the rest wait for the first
+    // coupling launch (stored or recompressed coupling)
+    int32_t n_near_head = 0;
     int32_t rt_leaf = 1;
     // LDS each FP32 generated-coupling workgroup reserves beyond its own
     // arrays: a quarter of a CU's, so that at most three share a CU (their
@@ -288,6 +291,11 @@ struct h2dlp_ctx {
 };
 
 namespace {
+
+// Share of the near-field entries (stored or recompressed coupling) launched
+// after the first coupling launch instead of at the fork: they keep HBM busy
+// during the second coupling launch and the downward pass, which move little.
+constexpr double kNearTail = 0.3;
 
 // Host part of a build: block structure, level-order numbering, pool layouts
 // and block descriptors, byte counts.  No HIP call.
@@ -459,6 +467,20 @@ int plan_impl(h2dlp_ctx* h, const h2dlp_mesh* mesh, const h2dlp_options* o) {
     // leaves whatever their level, and share source rows of x in that L2
     std::stable_sort(h->items_near.begin(), h->items_near.end(),
                      [](const ItemDesc& a, const ItemDesc& b) { return a.out_row < b.out_row; });
+    {
+        // the last kNearTail of the near-field entries run after the first
+        // coupling launch, beside the latency-bound passes that follow it
+        std::vector<int64_t> cum(h->items_near.size() + 1, 0);
+        for (size_t q = 0; q < h->items_near.size(); ++q) {
+            const ItemDesc& d = h->items_near[q];
+            int64_t e = 0;
+            for (int32_t b = d.blk_begin; b < d.blk_end; ++b) e += int64_t(d.m) * h->blks_leaf[b].k;
+            cum[q + 1] = cum[q] + e;
+        }
+        size_t head = 0;
+        while (head < h->items_near.size() && double(cum[head]) < (1.0 - kNearTail) * double(cum.back())) ++head;
+        h->n_near_head = int32_t(head);
+    }
     h->rt_leaf = (o->leaf + 15) / 16;
     h->off_v = off_v;
     h->off_wt = off_wt;
@@ -840,19 +862,21 @@ int materialize_impl(h2dlp_ctx* h, hipStream_t stream) {
     NearDesc* d_near = tmp(h->upload(h->nears, &scratch, stream));
 
     DevMesh dm{d_xyz, d_tri, d_inc_off, d_inc_tri, d_inc_loc, d_tgeo, h->d_perm};
+    int max_leaf = 1;
+    for (const LeafDesc& L : h->leaves) max_leaf = std::max(max_leaf, int(L.n));
     check(launch_tri_geometry(d_xyz, d_tri, T, d_tgeo, stream), "triangle geometry");
     check(launch_diagonal(dm, N, h->d_diag, stream), "diagonal");
     if (rec) {
         double* wt64 = tmp(h->alloc<double>(sizeof(double) * size_t(h->off_wt), &scratch));
         double* v64 = tmp(h->alloc<double>(sizeof(double) * size_t(h->off_v), &scratch));
         check(launch_build_wt(dm, d_boxes, m, d_quad, int(quad.size() / 3), d_leaves, int64_t(h->leaves.size()),
-                              P_FP64, wt64, stream), "column basis");
+                              max_leaf, P_FP64, wt64, stream), "column basis");
         check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), P_FP64, v64, stream),
               "row basis");
         recompress_impl(h, d_boxes, wt64, v64, &kept, stream);
     } else {
         check(launch_build_wt(dm, d_boxes, m, d_quad, int(quad.size() / 3), d_leaves, int64_t(h->leaves.size()),
-                              h->prec, h->d_pool_wt, stream), "column basis");
+                              max_leaf, h->prec, h->d_pool_wt, stream), "column basis");
         if (!h->regen_v)
             check(launch_build_v(dm, d_boxes, m, d_vleaves, int64_t(h->vleaves.size()), h->prec, h->d_pool_leaf,
                                  stream),
@@ -1037,8 +1061,8 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         // waits for the upward pass, which it would otherwise slow more than
         // it gains.
         const bool near_early = h->d_cgeo == nullptr;
-        ProductArgs nearp{h->d_items_near, h->n_items_leaf, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, nullptr,
-                          nullptr};
+        const int32_t near_head = near_early ? h->n_near_head : h->n_items_leaf;
+        ProductArgs nearp{h->d_items_near, near_head, h->rt_leaf, h->d_blks_leaf, h->d_pool_leaf, x, nullptr, nullptr};
         check(hipEventRecord(h->fork_ev, s), "event record");
         check(hipStreamWaitEvent(h->side, h->fork_ev, 0), "fork");
         rec_begin(h, h->side, 6, &ev);
@@ -1086,12 +1110,24 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
             check(launch_product_near(nearp, y64, prec, h->side), "near field");
             rec_end(h, h->side, 6, ev);
         }
-        check(hipEventRecord(h->join_ev, h->side), "event record");
+        // the near-field tail, on the side stream once the first coupling launch is enqueued
+        auto near_tail = [&]() {
+            if (!near_early || h->n_near_head >= h->n_items_leaf) return;
+            check(hipEventRecord(h->mid_ev, s), "event record");
+            check(hipStreamWaitEvent(h->side, h->mid_ev, 0), "fork");
+            ProductArgs tail{h->d_items_near + h->n_near_head, h->n_items_leaf - h->n_near_head, h->rt_leaf,
+                             h->d_blks_leaf, h->d_pool_leaf, x, nullptr, nullptr};
+            hipEvent_t ev6 = nullptr;
+            rec_begin(h, h->side, 6, &ev6);
+            check(launch_product_near(tail, y64, prec, h->side), "near field");
+            rec_end(h, h->side, 6, ev6);
+        };
 
         rec_begin(h, s, 3, &ev);
         if (h->rec) {
             ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, h->rt_cpl, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
             check(launch_product_store(cpl, prec, false, s), "coupling");
+            near_tail();
             if (cut > 0) {
                 check(hipStreamWaitEvent(s, h->upper_ev, 0), "join");
                 ProductArgs cpl_b{h->d_items_cpl_b, h->n_items_cpl_b, h->rt_cpl, h->d_blks_cpl, h->d_pool_s, xh,
@@ -1105,8 +1141,10 @@ int apply_impl(h2dlp_ctx* h, const void* u1, void* u2, int nrhs, int io, hipStre
         } else {
             ProductArgs cpl{h->d_items_cpl, h->n_items_cpl, (k + 15) / 16, h->d_blks_cpl, h->d_pool_s, xh, nullptr, yh};
             check(launch_coupling(cpl, k, prec, s), "coupling");
+            near_tail();
         }
         rec_end(h, s, 3, ev);
+        check(hipEventRecord(h->join_ev, h->side), "event record");
 
         if (h->rec) {          // y^_c += F_c y^_parent, a grouped product per level
             for (int l = 1; l <= h->S.depth; ++l) {

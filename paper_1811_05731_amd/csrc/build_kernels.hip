@@ -174,44 +174,83 @@ __global__ void __launch_bounds__(kBuildThreads) k_build_v(DevMesh mesh, const d
 // Transposed column basis of a leaf: A(mu, j) = W(j, mu) =
 //   sum_{T incident to j} 2 A_T sum_q w_q phi_j(y_q) n_T . grad L^s_mu(y_q);
 // block k x n_s.  quad: (u, v, weight) on the reference triangle, exact for the
-// polynomial integrand.
-__global__ void __launch_bounds__(kBuildThreads) k_build_wt(DevMesh mesh, const double* boxes, int m,
-                                                            const double* quad, int n_quad, const LeafDesc* leaves,
-                                                            int prec, void* pool) {
-    __shared__ double pts[3][8];
-    const LeafDesc L = leaves[blockIdx.x];
-    const double* box = boxes + 6 * int64_t(L.gid);
-    if (threadIdx.x < 3) cheb_axis(box, threadIdx.x, m, pts[threadIdx.x]);
+// polynomial integrand.  One 64-lane workgroup per node j of a leaf: for each
+// incident triangle the lanes first tabulate the 1D Lagrange values and
+// derivatives of the three axes at every quadrature point (LDS, from the
+// reciprocal differences of the leaf's Chebyshev points), then lane mu sums
+// its entries over the points.  tab: n_quad x 3 x 2m doubles (dynamic LDS).
+__global__ void __launch_bounds__(64) k_build_wt(DevMesh mesh, const double* boxes, int m, const double* quad,
+                                                 int n_quad, const LeafDesc* leaves, int prec, void* pool) {
+    extern __shared__ double tab[];
+    __shared__ double pts[3][8], inv[3][8][8];
+    const LeafDesc* L = leaves + blockIdx.x;
+    const int n = L->n, j = int(blockIdx.y);
+    if (j >= n) return;                       // uniform over the workgroup
+    const double* box = boxes + 6 * int64_t(L->gid);
+    const int t = int(threadIdx.x);
+    if (t < 3 * m) pts[t / m][t % m] = cheb_point(box, t / m, m, t % m);
+    __syncthreads();
+    for (int e = t; e < 3 * m * m; e += 64) {
+        const int a = e / (m * m), l = (e / m) % m, p = e % m;
+        inv[a][l][p] = l == p ? 0.0 : 1.0 / (pts[a][l] - pts[a][p]);
+    }
     __syncthreads();
     const int k = m * m * m;
-    for (int e = threadIdx.x; e < L.n * k; e += blockDim.x) {
-        const int j = e / k, mu = e % k;
-        const int l3[3] = {mu % m, (mu / m) % m, mu / (m * m)};
-        const int32_t node = mesh.perm[L.pos + j];
-        double total = 0.0;
-        for (int64_t q = mesh.inc_off[node]; q < mesh.inc_off[node + 1]; ++q) {
-            const int64_t T = mesh.inc_tri[q];
-            const int loc = mesh.inc_loc[q];
-            const double* r1 = mesh.xyz + 3 * int64_t(mesh.tri[3 * T]);
-            const double* r2 = mesh.xyz + 3 * int64_t(mesh.tri[3 * T + 1]);
-            const double* r3 = mesh.xyz + 3 * int64_t(mesh.tri[3 * T + 2]);
-            const double* g = mesh.tgeo + 4 * T;
+    const int32_t node = mesh.perm[L->pos + j];
+    double total[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s) total[s] = 0.0;
+    for (int64_t qi = mesh.inc_off[node]; qi < mesh.inc_off[node + 1]; ++qi) {
+        const int64_t T = mesh.inc_tri[qi];
+        const int loc = mesh.inc_loc[qi];
+        const double* r1 = mesh.xyz + 3 * int64_t(mesh.tri[3 * T]);
+        const double* r2 = mesh.xyz + 3 * int64_t(mesh.tri[3 * T + 1]);
+        const double* r3 = mesh.xyz + 3 * int64_t(mesh.tri[3 * T + 2]);
+        const double* g = mesh.tgeo + 4 * T;
+        for (int e = t; e < 3 * n_quad; e += 64) {
+            const int qq = e / 3, a = e % 3;
+            const double u = quad[3 * qq], v = quad[3 * qq + 1];
+            const double y = r1[a] + u * (r2[a] - r1[a]) + v * (r3[a] - r1[a]);
+            double* fv = tab + int64_t(e) * 2 * m;
+            for (int l = 0; l < m; ++l) {
+                double f = 1.0, d = 0.0;
+                for (int p = 0; p < m; ++p) {
+                    if (p == l) continue;
+                    f *= (y - pts[a][p]) * inv[a][l][p];
+                    double dp = inv[a][l][p];
+                    for (int q2 = 0; q2 < m; ++q2)
+                        if (q2 != l && q2 != p) dp *= (y - pts[a][q2]) * inv[a][l][q2];
+                    d += dp;
+                }
+                fv[l] = f;
+                fv[m + l] = d;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+            const int mu = t + 64 * s;
+            if (mu >= k) break;
+            const int lx = mu % m, ly = (mu / m) % m, lz = mu / (m * m);
             double acc = 0.0;
             for (int qq = 0; qq < n_quad; ++qq) {
                 const double u = quad[3 * qq], v = quad[3 * qq + 1], w = quad[3 * qq + 2];
-                double y[3], f[3], d[3];
-                for (int a = 0; a < 3; ++a) {
-                    y[a] = r1[a] + u * (r2[a] - r1[a]) + v * (r3[a] - r1[a]);
-                    f[a] = lagrange(pts[a], m, l3[a], y[a]);
-                    d[a] = lagrange_d(pts[a], m, l3[a], y[a]);
-                }
+                const double* tx = tab + int64_t(3 * qq) * 2 * m;
+                const double* ty = tx + 2 * m;
+                const double* tz = ty + 2 * m;
+                const double fx = tx[lx], fy = ty[ly], fz = tz[lz];
+                const double dn = g[0] * tx[m + lx] * fy * fz + g[1] * fx * ty[m + ly] * fz + g[2] * fx * fy * tz[m + lz];
                 const double phi = loc == 0 ? 1.0 - u - v : (loc == 1 ? u : v);
-                const double dn = g[0] * d[0] * f[1] * f[2] + g[1] * f[0] * d[1] * f[2] + g[2] * f[0] * f[1] * d[2];
                 acc += w * phi * dn;
             }
-            total += 2.0 * g[3] * acc;
+            total[s] += 2.0 * g[3] * acc;
         }
-        put_prec(pool, L.a_off + a_offset(k, L.n, mu, j), total, prec);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+        const int mu = t + 64 * s;
+        if (mu < k) put_prec(pool, L->a_off + a_offset(k, n, mu, j), total[s], prec);
     }
 }
 
@@ -341,10 +380,14 @@ hipError_t launch_build_v(DevMesh mesh, const double* boxes, int m, const LeafDe
 }
 
 hipError_t launch_build_wt(DevMesh mesh, const double* boxes, int m, const double* quad, int n_quad,
-                           const LeafDesc* leaves, int64_t n_leaves, int prec, void* pool, hipStream_t st) {
+                           const LeafDesc* leaves, int64_t n_leaves, int max_leaf, int prec, void* pool,
+                           hipStream_t st) {
     if (n_leaves == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_build_wt, dim3(unsigned(n_leaves)), dim3(kBuildThreads), 0, st, mesh, boxes, m, quad, n_quad,
-                       leaves, prec, pool);
+    if (max_leaf < 1 || max_leaf > 64 || m < 1 || m > 8) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * size_t(n_quad) * 6 * size_t(m);
+    if (lds > 60 * 1024) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_build_wt, dim3(unsigned(n_leaves), unsigned(max_leaf)), dim3(64), lds, st, mesh, boxes, m,
+                       quad, n_quad, leaves, prec, pool);
     return hipGetLastError();
 }
 

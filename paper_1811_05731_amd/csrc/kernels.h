@@ -47,8 +47,10 @@ hipError_t launch_tri_geometry(const double* xyz, const int32_t* tri, int64_t n_
 hipError_t launch_diagonal(DevMesh mesh, int64_t n_nodes, double* diag, hipStream_t st);
 hipError_t launch_build_v(DevMesh mesh, const double* boxes, int m, const LeafDesc* leaves, int64_t n_leaves,
                           int prec, void* pool, hipStream_t st);
+// max_leaf: the most nodes of any leaf (at most 64)
 hipError_t launch_build_wt(DevMesh mesh, const double* boxes, int m, const double* quad, int n_quad,
-                           const LeafDesc* leaves, int64_t n_leaves, int prec, void* pool, hipStream_t st);
+                           const LeafDesc* leaves, int64_t n_leaves, int max_leaf, int prec, void* pool,
+                           hipStream_t st);
 hipError_t launch_build_transfer(const double* boxes, const int32_t* parent, int64_t n_clusters, int m, int prec,
                                  void* e, hipStream_t st);
 hipError_t launch_build_coupling(const double* boxes, int m, int kp, const FarDesc* far, int64_t n_far, int prec,
