@@ -19,14 +19,59 @@ with a CPU stand-in.
 """
 from __future__ import annotations
 
+import os
+import threading
 import time
 from collections import deque
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field
 from typing import Any, Optional
 
 import numpy as np
 
 __all__ = ["MeshSpec", "Request", "Backend", "GpuBackend", "Server", "percentile"]
+
+
+# Host-side copies and checks of large batches are split over a few threads
+# (NumPy releases the GIL inside them): one thread moves ~10 GB/s, and a batch
+# on a large mesh is tens of megabytes.
+_PAR_BYTES = 1 << 20
+_pool_lock = threading.Lock()
+_pool_obj: Optional[ThreadPoolExecutor] = None
+
+
+def _pool() -> ThreadPoolExecutor:
+    global _pool_obj
+    with _pool_lock:
+        if _pool_obj is None:
+            _pool_obj = ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1)))
+        return _pool_obj
+
+
+def _row_chunks(rows: int, nbytes: int):
+    n = 1 if nbytes < _PAR_BYTES else min(rows, _pool()._max_workers)
+    b = np.linspace(0, rows, n + 1).astype(int)
+    return [(int(b[q]), int(b[q + 1])) for q in range(n) if b[q + 1] > b[q]]
+
+
+def copy_rows(dst: np.ndarray, src: np.ndarray) -> None:
+    """dst[...] = src (same 2-D shape), split by rows over the pool when large."""
+    chunks = _row_chunks(src.shape[0], src.nbytes)
+    if len(chunks) == 1:
+        dst[...] = src
+        return
+    list(_pool().map(lambda c: dst[c[0]:c[1]].__setitem__(Ellipsis, src[c[0]:c[1]]), chunks))
+
+
+def all_finite(u: np.ndarray) -> bool:
+    """No NaN or infinity in u (a sum per row chunk: one pass, no mask array;
+    a sum that overflows counts as non-finite too)."""
+    def part(c):
+        with np.errstate(over="ignore", invalid="ignore"):
+            return np.add.reduce(u[c[0]:c[1]], axis=None)
+    chunks = _row_chunks(u.shape[0], u.nbytes)
+    sums = list(_pool().map(part, chunks)) if len(chunks) > 1 else [part(chunks[0])]
+    return bool(np.all(np.isfinite(sums)))
 
 
 @dataclass
@@ -93,7 +138,8 @@ class Backend:
     def staging_bytes(self, max_values: int) -> int:            # device bytes per slot beyond the workspace
         return 0
 
-    def launch(self, slot, op, u1: np.ndarray) -> Any:       # -> ticket
+    def launch(self, slot, op, parts: list) -> Any:         # -> ticket
+        """Apply op to the batch: `parts` are the requests' (r_i x n) arrays, stacked in order."""
         raise NotImplementedError
 
     def poll(self, ticket) -> bool:
@@ -164,14 +210,17 @@ class GpuBackend(Backend):
                           "d_out": t.empty(v, dtype=t.float64, device=self.device)})
         return slots
 
-    def launch(self, slot, op, u1):
+    def launch(self, slot, op, parts):
         t = self.torch
         s = slot["stream"]
-        r, n = u1.shape
+        r, n = sum(p.shape[0] for p in parts), parts[0].shape[1]
         if r * n > slot["h_in"].numel():
             raise ValueError("batch larger than the slot's staging buffers")
         h_in = slot["h_in"][:r * n].view(r, n)
-        h_in.numpy()[...] = u1
+        staged, c = h_in.numpy(), 0
+        for p in parts:                             # each request straight into pinned memory
+            copy_rows(staged[c:c + p.shape[0]], p)
+            c += p.shape[0]
         d1 = slot["d_in"][:r * n].view(r, n)
         d2 = slot["d_out"][:r * n].view(r, n)
         h_out = slot["h_out"][:r * n].view(r, n)
@@ -191,7 +240,10 @@ class GpuBackend(Backend):
 
     def collect(self, ticket):
         ticket["ev"][3].synchronize()
-        return ticket["h_out"].numpy().copy()
+        src = ticket["h_out"].numpy()
+        out = np.empty(src.shape, dtype=src.dtype)
+        copy_rows(out, src)
+        return out
 
     def timings(self, ticket):
         ev, rel = ticket["ev"], ticket["reload_ev"]
@@ -313,10 +365,12 @@ class Server:
         return True
 
     def prewarm(self):
-        """Build every registered operator once (a geometry's operator is set up
-        before its first request); operators beyond the budget end up offloaded."""
+        """Make every registered operator resident before the first request: build
+        it, or reload it if it was built and parked when registered (reloads
+        without a slot return when the copies are done).  Operators beyond the
+        budget end up offloaded."""
         for m in self.meshes.values():
-            if m.op is None and self._fits(m):
+            if not m.on_device and self._fits(m):
                 self._make_resident(m)
 
     # -- the loop -------------------------------------------------------------------
@@ -334,7 +388,7 @@ class Server:
             return self._reject(req, f"u1 must have shape (r, {m.spec.n_nodes})")
         if u.shape[0] > self.max_batch_rhs:
             return self._reject(req, f"more than max_batch_rhs = {self.max_batch_rhs} columns")
-        if not np.all(np.isfinite(u)):
+        if not all_finite(u):
             return self._reject(req, "u1 has non-finite values")
         if not self._fits(m):
             return self._reject(req, "operator larger than the HBM budget")
@@ -367,10 +421,10 @@ class Server:
                     r = m.queue.popleft()
                     batch.append(r)
                     cols += r.nrhs
-                u = np.concatenate([np.atleast_2d(r.u1) for r in batch], axis=0)
+                parts = [np.atleast_2d(r.u1) for r in batch]
                 self.free_slots.pop()
                 try:
-                    ticket = self.backend.launch(slot, m.op, u)
+                    ticket = self.backend.launch(slot, m.op, parts)
                 except Exception as e:
                     self.free_slots.append(slot)
                     for r in batch:

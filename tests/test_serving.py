@@ -59,7 +59,8 @@ class FakeBackend(Backend):
         self._grow(n * workspace_bytes)
         return [{"id": q} for q in range(n)]
 
-    def launch(self, slot, op, u1):
+    def launch(self, slot, op, parts):
+        u1 = np.concatenate(parts, axis=0)
         assert op.on_device, "apply on an operator that is not resident"
         if self.fail_launch_on is not None and op.mesh_id == self.fail_launch_on:
             raise RuntimeError("injected launch failure")
@@ -221,3 +222,20 @@ def test_request_wider_than_batch_limit_is_rejected():
     reqs = [Request(0, "a", np.ones((4, 30)), 0.0), Request(1, "a", np.ones((3, 30)), 0.0)]
     stats = srv.run(reqs)
     assert reqs[0].error and reqs[1].error is None and stats["served"] == 1
+
+
+def test_host_copy_and_finite_check_large_and_small():
+    from paper_1811_05731_amd.serving import all_finite, copy_rows
+    g = np.random.default_rng(3)
+    for rows, n in ((3, 50), (16, 40000), (64, 5000)):         # below and above the threaded size
+        u = g.normal(size=(rows, n))
+        dst = np.empty_like(u)
+        copy_rows(dst, u)
+        assert np.array_equal(dst, u)
+        assert all_finite(u)
+        for bad in (np.nan, np.inf, -np.inf):
+            v = u.copy()
+            v[g.integers(rows), g.integers(n)] = bad
+            assert not all_finite(v)
+    w = np.full((2, 4), 1e308)                                  # finite entries whose sum overflows
+    assert not all_finite(w)
