@@ -170,15 +170,19 @@ __device__ inline double wave_sum(double v) {
 // also when the rows are rank-deficient (an unpivoted reflection from a zero
 // pivot would spread content into later rows).  A reflection touches only
 // R(j, :) and the chunk (R is triangular), so both stay in LDS; R(j, j) keeps
-// the sign the reflection gives.  2 threads per column apply a reflection
-// (half the chunk rows each).
-__global__ void __launch_bounds__(256) k_fold(const FoldDesc* __restrict__ desc, int k) {
+// the sign the reflection gives.  kFoldTpc threads per column apply a
+// reflection (kFoldChunk / kFoldTpc chunk rows each); the workgroup is
+// kFoldThreads wide, since its LDS admits one per CU anyway.
+constexpr int kFoldThreads = 1024;
+constexpr int kFoldTpc = 8;
+static_assert(kFoldThreads / kFoldTpc >= 128, "one thread group per column of k <= 128");
+__global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldDesc* __restrict__ desc, int k) {
     extern __shared__ double sm[];
     double* Rs = sm;                        // k x k row-major
     double* Cs = Rs + k * k;                // kFoldChunk x k row-major
     double* us = Cs + kFoldChunk * k;       // the reflection's chunk part
     __shared__ double s_tau;
-    const FoldDesc d = desc[blockIdx.x];
+    const FoldDesc& d = desc[blockIdx.x];       // read in place: its segment arrays are indexed at run time
     const int tid = threadIdx.x;
     int filled = min(max(d.init, 0), k);
     for (int e = tid; e < k * k; e += blockDim.x) {
@@ -226,15 +230,15 @@ __global__ void __launch_bounds__(256) k_fold(const FoldDesc* __restrict__ desc,
             }
             __syncthreads();
             const double tau = s_tau;
-            const int l = j + 1 + (tid >> 1), h = tid & 1;
+            const int l = j + 1 + tid / kFoldTpc, h = tid % kFoldTpc;
             if (l < k && (tau != 0.0 || mv >= 0)) {
                 const double r0 = mv >= 0 ? Cs[mv * k + l] : Rs[j * k + l];
                 double w = 0.0;
                 if (tau != 0.0) {
-                    constexpr int H = kFoldChunk / 2;
+                    constexpr int H = kFoldChunk / kFoldTpc;
 #pragma unroll
                     for (int i = 0; i < H; ++i) w += us[h * H + i] * Cs[(h * H + i) * k + l];
-                    w += __shfl_xor(w, 1);
+                    for (int o = 1; o < kFoldTpc; o <<= 1) w += __shfl_xor(w, o);
                     w = tau * (w + r0);
 #pragma unroll
                     for (int i = 0; i < H; ++i) Cs[(h * H + i) * k + l] -= w * us[h * H + i];
@@ -257,48 +261,75 @@ __global__ void __launch_bounds__(256) k_fold(const FoldDesc* __restrict__ desc,
 // Singular values and right singular vectors of a k x k matrix M (column-
 // major, ld k): one-sided Jacobi rotations of the columns of A = M^T until
 // they are orthogonal (A J = W); then the normalised columns of W are the
-// right singular vectors of M and their norms the singular values.  Pairs
-// follow the circle method (n - 1 steps of n/2 disjoint pairs per sweep, n =
-// k rounded up to even, the extra column zero); 4 threads share a pair.
-// Output: sigma descending, V with the matching columns (zero for sigma = 0).
-__global__ void __launch_bounds__(256) k_jacobi(double* const* __restrict__ Ms, int k, double* __restrict__ sig,
-                                               double* __restrict__ V) {
+// right singular vectors of M and their norms the singular values.  Only the
+// columns of A that hold a nonzero (the rows of M that can be nonzero: the
+// rows folded into R_Y, at most min(rows of Y, k)) take part; the others are
+// zero and stay so.  Pairs of those nz columns follow the circle method
+// (n - 1 steps of n/2 disjoint pairs per sweep, n = nz rounded up to even,
+// the spare column k standing in as the zero one); tpp threads share a pair,
+// as many as the kJacThreads of the workgroup allow (its LDS admits one per
+// CU).  Output: sigma descending, V with the matching columns (zero for
+// sigma = 0).
+constexpr int kJacThreads = 1024;
+__global__ void __launch_bounds__(kJacThreads) k_jacobi(double* const* __restrict__ Ms, int k,
+                                                       double* __restrict__ sig, double* __restrict__ V) {
     extern __shared__ double sm[];
-    const int n = (k + 1) & ~1;
-    double* A = sm;                         // n columns of k rows, column c at A + c k
-    double* nrm = A + int64_t(n) * k;       // n
-    __shared__ int s_rot;
+    const int na = k + 1;                   // columns in LDS: A's k and a spare zero one
+    double* A = sm;                         // column c at A + c k
+    double* nrm = A + int64_t(na) * k;      // na
+    int* idx = reinterpret_cast<int*>(nrm + na);    // na: the columns that take part, then the spare
+    __shared__ int s_rot, s_nz;
     const double* M = Ms[blockIdx.x];
     const int tid = threadIdx.x;
-    for (int e = tid; e < n * k; e += blockDim.x) {
+    for (int e = tid; e < na * k; e += blockDim.x) {
         const int c = e / k, r = e % k;     // A(r, c) = M(c, r)
         A[e] = c < k ? M[c + int64_t(k) * r] : 0.0;
     }
-    const int p = tid >> 2, q = tid & 3;
-    for (int sweep = 0; sweep < 60; ++sweep) {
+    __syncthreads();
+    for (int c = tid; c < k; c += blockDim.x) {
+        bool any = false;
+        for (int r = 0; r < k && !any; ++r) any = A[int64_t(c) * k + r] != 0.0;
+        nrm[c] = any ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int nz = 0;
+        for (int c = 0; c < k; ++c)
+            if (nrm[c] != 0.0) idx[nz++] = c;
+        idx[nz] = k;                        // the spare zero column, used when nz is odd
+        s_nz = nz;
+    }
+    __syncthreads();
+    const int n = (s_nz + 1) & ~1;
+    int tpp = 32;                           // threads per pair: a power of two, (n / 2) tpp <= kJacThreads
+    while (tpp > 1 && (n / 2) * tpp > kJacThreads) tpp >>= 1;
+    const int p = tid / tpp, q = tid % tpp;
+    for (int sweep = 0; sweep < 60 && n > 1; ++sweep) {
         if (tid == 0) s_rot = 0;
         __syncthreads();
         for (int step = 0; step < n - 1; ++step) {
             if (p < n / 2) {
                 const int a = p == 0 ? step : (step + p) % (n - 1);
                 const int b = p == 0 ? n - 1 : (step - p + (n - 1)) % (n - 1);
-                double* ca = A + int64_t(a) * k;
-                double* cb = A + int64_t(b) * k;
+                double* ca = A + int64_t(idx[a]) * k;
+                double* cb = A + int64_t(idx[b]) * k;
                 double aa = 0.0, bb = 0.0, ab = 0.0;
-                for (int r = q; r < k; r += 4) {
+                for (int r = q; r < k; r += tpp) {
                     const double x = ca[r], y = cb[r];
                     aa += x * x;
                     bb += y * y;
                     ab += x * y;
                 }
-                aa += __shfl_xor(aa, 1); aa += __shfl_xor(aa, 2);
-                bb += __shfl_xor(bb, 1); bb += __shfl_xor(bb, 2);
-                ab += __shfl_xor(ab, 1); ab += __shfl_xor(ab, 2);
+                for (int o = 1; o < tpp; o <<= 1) {
+                    aa += __shfl_xor(aa, o);
+                    bb += __shfl_xor(bb, o);
+                    ab += __shfl_xor(ab, o);
+                }
                 if (ab != 0.0 && fabs(ab) > 4e-15 * sqrt(aa * bb)) {
                     const double zeta = (bb - aa) / (2.0 * ab);
                     const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
                     const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-                    for (int r = q; r < k; r += 4) {
+                    for (int r = q; r < k; r += tpp) {
                         const double x = ca[r], y = cb[r];
                         ca[r] = cs * x - sn * y;
                         cb[r] = sn * x + cs * y;
@@ -312,7 +343,7 @@ __global__ void __launch_bounds__(256) k_jacobi(double* const* __restrict__ Ms, 
         __syncthreads();                    // every thread has read s_rot before it is reset
         if (!rotated) break;
     }
-    for (int c = tid; c < n; c += blockDim.x) {
+    for (int c = tid; c < k; c += blockDim.x) {
         double s2 = 0.0;
         for (int r = 0; r < k; ++r) s2 += A[int64_t(c) * k + r] * A[int64_t(c) * k + r];
         nrm[c] = sqrt(s2);
@@ -432,7 +463,7 @@ std::string recompress(const RecompressPlan& P, const double* d_boxes, const dou
     const int64_t kk = int64_t(k) * k, rk = int64_t(rows) * k;
     if (k < 1 || k > 128 || rows < 2 * k) return "recompression needs k <= 128 and rows >= 2k";
     const size_t lds_fold = sizeof(double) * (size_t(k) * k + size_t(kFoldChunk) * k + kFoldChunk);
-    const size_t lds_jac = sizeof(double) * (size_t((k + 1) & ~1) * k + ((k + 1) & ~1));
+    const size_t lds_jac = sizeof(double) * (size_t(k + 1) * k + (k + 1)) + sizeof(int) * size_t(k + 1);
     {
         int dev = 0, lds = 0;
         if (!c.hip(hipGetDevice(&dev), "device") ||
@@ -494,7 +525,7 @@ std::string recompress(const RecompressPlan& P, const double* d_boxes, const dou
     const auto N = rocblas_operation_none, T = rocblas_operation_transpose;
     auto fold = [&](const std::vector<FoldDesc>& d) {
         if (d.empty() || !c.put(d_fold, d)) return;
-        hipLaunchKernelGGL(k_fold, dim3(unsigned(d.size())), dim3(256), lds_fold, stream, d_fold, k);
+        hipLaunchKernelGGL(k_fold, dim3(unsigned(d.size())), dim3(kFoldThreads), lds_fold, stream, d_fold, k);
         c.hip(hipGetLastError(), "fold");
     };
 
@@ -654,7 +685,7 @@ std::string recompress(const RecompressPlan& P, const double* d_boxes, const dou
             std::vector<double*> mp(n);
             for (int32_t q = 0; q < n; ++q) mp[q] = Mx + int64_t(q) * kk;
             if (!c.put(dptr, mp)) break;
-            hipLaunchKernelGGL(k_jacobi, dim3(n), dim3(256), lds_jac, stream, dptr, k, sig, Vz);
+            hipLaunchKernelGGL(k_jacobi, dim3(n), dim3(kJacThreads), lds_jac, stream, dptr, k, sig, Vz);
             c.hip(hipGetLastError(), "jacobi");
             hsig.resize(size_t(n) * k);
             if (!c.hip(hipMemcpyAsync(hsig.data(), sig, hsig.size() * sizeof(double), hipMemcpyDeviceToHost, stream),
