@@ -526,21 +526,26 @@ def near_field_alg_bytes(st, elem: int, n_nodes: int) -> int:
     return st.bytes_near + vec
 
 
-def near_field_roofline(st, prec: str, kernels: dict, n_nodes: int) -> dict:
-    """Roofline record of the near-field kernel from its HIP-event time."""
+def near_field_roofline(st, prec: str, kernels: dict, n_nodes: int, applies: int) -> dict:
+    """Roofline record of the near-field kernel from its HIP-event time.  A
+    "launch" is the kind's launches of one apply (the diagonal and the two
+    near-field launches, the second after the first coupling launch): their
+    HIP-event intervals summed over `applies` applies, divided by them."""
     ms_, n_ = kernels["near_field"]
-    avg = ms_ / max(n_, 1)
+    avg = ms_ / max(applies, 1)
     b = near_field_alg_bytes(st, 8 if prec == "fp64" else 4, n_nodes)
     ach = b / (avg * 1e-3) / 1e9
     return {"bound": "hbm", "kernel": "near_field", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "alg_bytes_per_launch": b, "avg_launch_ms": round(avg, 4),
+            "event_intervals_per_apply": round(n_ / max(applies, 1), 2),
             "roofline_ms": round(b / HBM_PEAK_GBS / 1e6, 4)}
 
 
-def roofline_of(st, prec: str, coupling: str, kernels: dict, n_nodes: int) -> dict:
-    """Roofline record of the coupling kernel from its HIP-event time."""
+def roofline_of(st, prec: str, coupling: str, kernels: dict, n_nodes: int, applies: int) -> dict:
+    """Roofline record of the coupling kernel from its HIP-event time (one
+    interval per apply around its launches: two when recompressed)."""
     cpl_ms, cpl_n = kernels["coupling"]
-    avg = cpl_ms / max(cpl_n, 1)
+    avg = cpl_ms / max(applies, 1)
     ev = 8 if prec == "fp64" else 4
     if coupling == "generated":            # no coupling bytes: bound by the MFMA pipe
         fl = coupling_flops(st)
@@ -699,8 +704,8 @@ def main():
     value = n * nrhs / (ms * 1e-3) / 1e9
     # the dominant kernel is the one with the longer roofline time (its
     # algorithmic work at its roofline's peak); both records are reported
-    rooflines = {"coupling": roofline_of(st, args.precision, args.coupling, kernels, n),
-                 "near_field": near_field_roofline(st, args.precision, kernels, n)}
+    rooflines = {"coupling": roofline_of(st, args.precision, args.coupling, kernels, n, args.steps),
+                 "near_field": near_field_roofline(st, args.precision, kernels, n, args.steps)}
     dominant = max(rooflines, key=lambda k_: rooflines[k_]["roofline_ms"])
     for kind, roof_k in rooflines.items():
         roof_k["traffic"] = None
@@ -768,7 +773,8 @@ def main():
             opv = build(prec, cpl, dmax, eps, rb)
             torch.cuda.synchronize()
             bs = time.perf_counter() - t0
-            msv, kv = time_path(opv, d_u1, d_u2, max(3, args.steps // 2), args.warmup, profile=("coupling",))
+            nv = max(3, args.steps // 2)
+            msv, kv = time_path(opv, d_u1, d_u2, nv, args.warmup, profile=("coupling",))
             key = ((prec if cpl == "stored" else f"{prec}_generated") + ("_plain" if dm == 0 and dmax == 0 and not eps
                                                                         else "")
                    + ("_recompressed" if eps else "") + ("_regenerated_v" if rb == "generated" else ""))
@@ -776,7 +782,7 @@ def main():
             ev = 8 if prec == "fp64" else 4
             variants[key] = {"value": round(n * nrhs / (msv * 1e-3) / 1e9, 4), "ms_per_step": round(msv, 4),
                              "dense_far_max": dmax, "recompress_eps": eps, "row_basis": rb, "build_s": round(bs, 2),
-                             "coupling": roofline_of(opv.stats, prec, cpl, kv, n),
+                             "coupling": roofline_of(opv.stats, prec, cpl, kv, n, nv),
                              "resident_GB": round(opv.stats.bytes_resident / 1e9, 2),
                              "apply_hbm_frac": round(apply_alg_bytes(opv.stats, ev, n, nrhs) / (msv * 1e-3) / 1e9
                                                      / HBM_PEAK_GBS, 4),

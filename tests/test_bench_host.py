@@ -22,20 +22,20 @@ def test_coupling_records():
     # generated: 2 flops per entry and right-hand side, 16 right-hand sides per pass
     flops = 2.0 * 10 * 125 ** 2 * 16
     assert bench.coupling_flops(st) == flops
-    r = bench.roofline_of(st, "fp32", "generated", {"coupling": (4.0, 2)}, 1000)    # 2 ms per launch
+    r = bench.roofline_of(st, "fp32", "generated", {"coupling": (4.0, 2)}, 1000, 2)    # 2 ms per apply
     assert r["bound"] == "mfma" and r["unit"] == "TFLOP/s" and r["peak"] == 157.3
     assert abs(r["achieved"] - flops / 2e-3 / 1e12) < 0.01
     assert abs(r["roofline_ms"] - flops / 157.3e12 * 1e3) < 1e-4
     # stored: every entry once, xhat read and yhat written once per cluster
     b = 10 * 125 ** 2 * 4 + 2 * 7 * 125 * 16 * 4
     assert bench.coupling_alg_bytes(st, 4, 4) == b
-    r = bench.roofline_of(st, "fp32", "stored", {"coupling": (1.0, 1)}, 1000)
+    r = bench.roofline_of(st, "fp32", "stored", {"coupling": (1.0, 1)}, 1000, 1)
     assert r["bound"] == "hbm" and r["alg_bytes_per_launch"] == b
     assert abs(r["frac"] - b / 1e-3 / 1e9 / 8000.0) < 1e-4
     # FP64 and BF16X6 entries are 8 and 6 bytes
-    assert bench.roofline_of(st, "fp64", "stored", {"coupling": (1.0, 1)}, 1000)["alg_bytes_per_launch"] == \
+    assert bench.roofline_of(st, "fp64", "stored", {"coupling": (1.0, 1)}, 1000, 1)["alg_bytes_per_launch"] == \
         10 * 125 ** 2 * 8 + 2 * 7 * 125 * 16 * 8
-    assert bench.roofline_of(st, "bf16x6", "stored", {"coupling": (1.0, 1)}, 1000)["alg_bytes_per_launch"] == \
+    assert bench.roofline_of(st, "bf16x6", "stored", {"coupling": (1.0, 1)}, 1000, 1)["alg_bytes_per_launch"] == \
         10 * 125 ** 2 * 6 + 2 * 7 * 125 * 16 * 4
 
 
@@ -46,8 +46,12 @@ def test_near_field_record():
     # the near-field product; D (8 B) per node
     assert bench.near_field_alg_bytes(st, 4, 100) == 10 ** 6 + 100 * 16 * 36 + 800
     assert bench.near_field_alg_bytes(st, 8, 100) == 10 ** 6 + 100 * 16 * 40 + 800
-    r = bench.near_field_roofline(st, "fp32", {"near_field": (3.0, 3)}, 100)
+    r = bench.near_field_roofline(st, "fp32", {"near_field": (3.0, 3)}, 100, 3)
     assert r["bound"] == "hbm" and abs(r["achieved"] - (10 ** 6 + 57600 + 800) / 1e-3 / 1e9) < 0.1
+    # two event intervals per apply (the launches before and after the first
+    # coupling launch): still 1 ms per apply
+    r2 = bench.near_field_roofline(st, "fp32", {"near_field": (3.0, 6)}, 100, 3)
+    assert r2["achieved"] == r["achieved"] and r2["avg_launch_ms"] == 1.0 and r2["event_intervals_per_apply"] == 2
 
 
 def test_more_than_one_gpu_is_refused():
