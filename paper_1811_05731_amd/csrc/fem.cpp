@@ -42,6 +42,10 @@ void hcheck(hipError_t e, const char* where) {
 }
 
 constexpr int kCheckEvery = 8;   // CG iterations between two reads of the residual
+// the preconditioner: Chebyshev steps on [lmax / kChebRatio, lmax] with lmax the
+// Gershgorin bound of D^-1 A (fem.h)
+constexpr int kChebDeg = 6;
+constexpr double kChebRatio = 100.0;
 
 }  // namespace
 
@@ -64,6 +68,8 @@ struct h2dlp_fem_ctx {
     double* d_dinv_fix = nullptr;
     int32_t* d_bnode = nullptr;
     double *d_b = nullptr, *d_r = nullptr, *d_z = nullptr, *d_p = nullptr, *d_q = nullptr, *d_ones = nullptr;
+    double *d_z2 = nullptr, *d_dk = nullptr;
+    double lambda_max = 0.0;                 // Gershgorin bound of D^-1 A (0: Jacobi)
     double *d_u1 = nullptr, *d_u2 = nullptr, *d_g = nullptr, *d_ub1 = nullptr, *d_ub2 = nullptr;
     double *d_part = nullptr, *d_S = nullptr;
     double* h_S = nullptr;                   // pinned copy of the scalars
@@ -121,8 +127,25 @@ struct h2dlp_fem_ctx {
         return d;
     }
     FemCg cg(const double* dinv) const {
-        return FemCg{n, d_ell_off, d_ell_w, d_ell_col, d_ell_val, dinv, d_r, d_z, d_p, d_q, d_part,
-                     d_part + kSpmvBlocks, d_part + kSpmvBlocks + kFemBlocks, d_S};
+        FemCg c{n, d_ell_off, d_ell_w, d_ell_col, d_ell_val, dinv, d_r, d_z, d_p, d_q, d_part,
+                d_part + kSpmvBlocks, d_part + kSpmvBlocks + kFemBlocks, d_S, d_z2, d_dk, 1, 1.0, {}, {}};
+        if (lambda_max > 0.0) {
+            // Chebyshev iteration on [lmin, lmax]: theta the midpoint, delta
+            // the half width, sigma = theta / delta; rho_0 = 1 / sigma and
+            // rho_k = 1 / (2 sigma - rho_{k-1})
+            const double lmax = lambda_max, lmin = lambda_max / kChebRatio;
+            const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+            c.deg = kChebDeg;
+            c.inv_theta = 1.0 / theta;
+            double rho = 1.0 / sigma;
+            for (int k = 1; k < kChebDeg; ++k) {
+                const double rho_k = 1.0 / (2.0 * sigma - rho);
+                c.c1[k] = rho_k * rho;
+                c.c2[k] = 2.0 * rho_k / delta;
+                rho = rho_k;
+            }
+        }
+        return c;
     }
 };
 
@@ -277,7 +300,8 @@ int fem_build_impl(h2dlp_fem_ctx* f, const h2dlp_volume* vol, const h2dlp_option
     hcheck(fem_stiffness(n, f->d_inc_off, f->d_inc, f->d_tet, f->d_geo, d_rowptr, d_col, d_val, st), "stiffness");
     hcheck(fem_dinv(n, d_rowptr, d_col, d_val, d_onb, f->d_dinv_free, f->d_dinv_fix, st), "diagonal");
     hcheck(fem_to_ell(n, d_rowptr, d_val, f->cg(f->d_dinv_free), f->d_ell_val, st), "sliced ELL");
-    for (double** v : {&f->d_b, &f->d_r, &f->d_z, &f->d_p, &f->d_q, &f->d_ones, &f->d_u1, &f->d_u2, &f->d_g})
+    for (double** v : {&f->d_b, &f->d_r, &f->d_z, &f->d_p, &f->d_q, &f->d_ones, &f->d_u1, &f->d_u2, &f->d_g,
+                       &f->d_z2, &f->d_dk})
         *v = f->alloc<double>(size_t(n));
     f->d_ub1 = f->alloc<double>(f->bnodes.size());
     f->d_ub2 = f->alloc<double>(f->bnodes.size());
@@ -289,7 +313,12 @@ int fem_build_impl(h2dlp_fem_ctx* f, const h2dlp_volume* vol, const h2dlp_option
         f->h_S = nullptr;
         throw std::bad_alloc();
     }
+    // the spectrum bound of D^-1 A for the preconditioner (it bounds the
+    // Dirichlet system's too: its rows are a subset with fewer columns)
+    hcheck(fem_gershgorin(f->cg(f->d_dinv_free), f->d_part, f->d_S, kSlotLambda, st), "spectrum bound");
+    hcheck(hipMemcpyAsync(f->h_S, f->d_S, sizeof(double) * kSlots, hipMemcpyDeviceToHost, st), "spectrum bound");
     hcheck(hipStreamSynchronize(st), "build");
+    f->lambda_max = f->h_S[kSlotLambda] > 0.0 && std::isfinite(f->h_S[kSlotLambda]) ? f->h_S[kSlotLambda] : 0.0;
     // build-only arrays: coordinates, boundary flags and the CSR form
     for (void* p : {static_cast<void*>(d_xyz), static_cast<void*>(d_onb), static_cast<void*>(d_rowptr),
                     static_cast<void*>(d_col), static_cast<void*>(d_val)})
@@ -322,9 +351,9 @@ hipGraphExec_t capture_steps(h2dlp_fem_ctx* f, const FemCg& c, double* x) {
     return e;
 }
 
-// Jacobi-preconditioned CG from zero on the rows with dinv != 0; returns the
-// iterations and the relative residual |r| / |r0|.  `graph`: kCheckEvery
-// iterations of this solve as one graph, or NULL.
+// Preconditioned CG (Chebyshev steps on D^-1 A, fem.h) from zero on the rows
+// with dinv != 0; returns the iterations and the relative residual |r| / |r0|.
+// `graph`: kCheckEvery iterations of this solve as one graph, or NULL.
 int cg_solve(h2dlp_fem_ctx* f, const FemCg& c, const double* b, double* x, double tol, int max_iter, hipStream_t st,
              hipGraphExec_t graph, int* iters, double* rel) {
     hcheck(fem_cg_start(c, b, x, st), "cg");

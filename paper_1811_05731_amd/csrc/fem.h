@@ -12,6 +12,7 @@ constexpr int kGeo = 13;                   // doubles per tetrahedron: volume, t
 constexpr unsigned kFemBlocks = 1024;      // blocks of the reducing vector kernels (their partials)
 constexpr unsigned kSpmvBlocks = 2048;     // most blocks of the matrix-vector product (one row a thread)
 constexpr int kSlice = 64;                 // rows of a sliced-ELL slice (one wavefront)
+constexpr int kMaxCheb = 8;                // largest degree of the Chebyshev preconditioner
 
 // slots of the device scalar array
 constexpr int kSlotRZ0 = 0;                // r . z of the current and of the next CG iteration (0, 1)
@@ -19,6 +20,7 @@ constexpr int kSlotRR = 2;                 // r . r after the last CG iteration
 constexpr int kSlotBB = 3;                 // b . b of the system being solved
 constexpr int kSlotMean = 4;               // a mean to remove
 constexpr int kSlotEnergy = 5;             // -(1/2) sum vol M . H
+constexpr int kSlotLambda = 6;             // the Gershgorin bound of D^-1 A (build)
 constexpr int kSlots = 8;
 
 // One preconditioned CG solve on the stiffness matrix, FP64 in sliced ELL:
@@ -26,6 +28,14 @@ constexpr int kSlots = 8;
 // slot k) at off[s] + 64 k + r, its columns in ascending order, padding with
 // the row's own column and 0.  Rows with dinv = 0 are fixed (their residual is
 // held at zero).
+//
+// Preconditioner: deg steps of the Chebyshev iteration for D^-1 A z = D^-1 r
+// from z = 0 on the interval [lmin, lmax] of D^-1 A's spectrum (D the
+// diagonal): z_0 = inv_theta D^-1 r, d_0 = z_0, then for k = 1 .. deg - 1
+// d_k = c1[k] d_{k-1} + c2[k] D^-1 (r - A z_{k-1}), z_k = z_{k-1} + d_k.
+// deg = 1 with inv_theta = 1 is the Jacobi preconditioner.  The polynomial is
+// positive on (0, lmax], so the preconditioner is symmetric positive definite
+// when lmax bounds the spectrum.
 struct FemCg {
     int64_t n;
     const int64_t* off;
@@ -37,6 +47,10 @@ struct FemCg {
     double *part_pq;                       // kSpmvBlocks (one per block of the matrix-vector product)
     double *part_rz, *part_rr;             // kFemBlocks each
     double* S;                             // kSlots
+    double *z2, *dk;                       // Chebyshev: the other z buffer and the step d_k
+    int deg;
+    double inv_theta;
+    double c1[kMaxCheb], c2[kMaxCheb];
 };
 
 hipError_t fem_geometry(int64_t n_tets, const double* xyz, const int32_t* tet, double* geo, hipStream_t st);
@@ -57,6 +71,9 @@ hipError_t fem_dot(int64_t n, const double* a, const double* b, double* part, do
 // x -= S[slot]
 hipError_t fem_shift(int64_t n, double* x, const double* S, int slot, hipStream_t st);
 hipError_t fem_cg_start(const FemCg& c, const double* b, double* x, hipStream_t st);
+// max over the rows with dinv != 0 of dinv_i sum_j |a_ij| (a bound of the
+// spectrum of D^-1 A by Gershgorin's theorem), into S[slot]
+hipError_t fem_gershgorin(const FemCg& c, double* part, double* S, int slot, hipStream_t st);
 hipError_t fem_cg_step(const FemCg& c, double* x, int iter, hipStream_t st);
 // y = A x (the partials of x . y land in c.part_pq)
 hipError_t fem_spmv(const FemCg& c, const double* x, double* y, hipStream_t st);

@@ -188,18 +188,20 @@ __global__ void __launch_bounds__(kT) k_shift(int64_t n, double* __restrict__ x,
 // Start of preconditioned CG from x = 0: r = mask(b), z = dinv r, p = z; the
 // partials of r . z and r . r
 __global__ void __launch_bounds__(kT) k_cg_start(int64_t n, const double* __restrict__ b,
-                                                const double* __restrict__ dinv, double* __restrict__ x,
-                                                double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
+                                                const double* __restrict__ dinv, double inv_theta,
+                                                double* __restrict__ x, double* __restrict__ r, double* __restrict__ z,
+                                                double* __restrict__ p, double* __restrict__ dk,
                                                 double* __restrict__ part_rz, double* __restrict__ part_rr) {
     __shared__ double sh[kT / 64 + 1];
     double rz = 0.0, rr = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT) {
         const double ri = dinv[i] != 0.0 ? b[i] : 0.0;
-        const double zi = dinv[i] * ri;
+        const double zi = inv_theta * (dinv[i] * ri);
         x[i] = 0.0;
         r[i] = ri;
         z[i] = zi;
         p[i] = zi;
+        if (dk) dk[i] = zi;
         rz += ri * zi;
         rr += ri * ri;
     }
@@ -210,12 +212,13 @@ __global__ void __launch_bounds__(kT) k_cg_start(int64_t n, const double* __rest
 }
 
 // alpha = rz / (p . q) from the matrix-vector product's partials; x += alpha
-// p, r -= alpha q (zero where fixed), z = dinv r; partials of the new r . z
-// and r . r
+// p, r -= alpha q (zero where fixed), z = inv_theta dinv r (and d = z for the
+// Chebyshev steps that follow); partials of the new r . z and r . r
 __global__ void __launch_bounds__(kT) k_cg_update(int64_t n, int nb, const double* __restrict__ part_pq,
                                                  const double* __restrict__ S, int rz_slot,
-                                                 const double* __restrict__ dinv, double* __restrict__ x,
-                                                 double* __restrict__ r, double* __restrict__ z,
+                                                 const double* __restrict__ dinv, double inv_theta,
+                                                 double* __restrict__ x, double* __restrict__ r,
+                                                 double* __restrict__ z, double* __restrict__ dk,
                                                  const double* __restrict__ p, const double* __restrict__ q,
                                                  double* __restrict__ part_rz, double* __restrict__ part_rr) {
     __shared__ double sh[kT / 64 + 1];
@@ -225,9 +228,10 @@ __global__ void __launch_bounds__(kT) k_cg_update(int64_t n, int nb, const doubl
     for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT) {
         x[i] += alpha * p[i];
         const double ri = dinv[i] != 0.0 ? r[i] - alpha * q[i] : 0.0;
-        const double zi = dinv[i] * ri;
+        const double zi = inv_theta * (dinv[i] * ri);
         r[i] = ri;
         z[i] = zi;
+        if (dk) dk[i] = zi;
         rz += ri * zi;
         rr += ri * ri;
     }
@@ -235,6 +239,76 @@ __global__ void __launch_bounds__(kT) k_cg_update(int64_t n, int nb, const doubl
     if (threadIdx.x == 0) part_rz[blockIdx.x] = t;
     t = block_sum(rr, sh);
     if (threadIdx.x == 0) part_rr[blockIdx.x] = t;
+}
+
+// One Chebyshev step of the preconditioner: per row, d = c1 d + c2 dinv (r -
+// A z_in), z_out = z_in + d (and p = z_out when p is given, at the start of
+// a solve); partials of r . z_out when part_rz is given (the last step).
+__global__ void __launch_bounds__(kT) k_cheb_step(int64_t n, const int64_t* __restrict__ off,
+                                                 const int32_t* __restrict__ width, const int32_t* __restrict__ col,
+                                                 const double* __restrict__ val, const double* __restrict__ dinv,
+                                                 const double* __restrict__ r, const double* __restrict__ zin,
+                                                 double* __restrict__ zout, double* __restrict__ dk, double c1,
+                                                 double c2, double* __restrict__ p, double* __restrict__ part_rz) {
+    __shared__ double sh[kT / 64 + 1];
+    double rz = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i - threadIdx.x < n; i += int64_t(gridDim.x) * kT) {
+        if (i < n) {
+            const int64_t sl = i / kSlice;
+            const int64_t base = off[sl] + (i - sl * kSlice);
+            const int w = width[sl];
+            double s = 0.0;
+#pragma unroll 4
+            for (int k = 0; k < w; ++k) s += val[base + int64_t(kSlice) * k] * zin[col[base + int64_t(kSlice) * k]];
+            const double d = c1 * dk[i] + c2 * (dinv[i] * (r[i] - s));
+            const double zo = zin[i] + d;
+            dk[i] = d;
+            zout[i] = zo;
+            if (p) p[i] = zo;
+            rz += r[i] * zo;
+        }
+    }
+    if (part_rz) {
+        const double t = block_sum(rz, sh);
+        if (threadIdx.x == 0) part_rz[blockIdx.x] = t;
+    }
+}
+
+// per block the largest dinv_i sum_j |a_ij| of its rows
+__global__ void __launch_bounds__(kT) k_gershgorin(int64_t n, const int64_t* __restrict__ off,
+                                                  const int32_t* __restrict__ width, const double* __restrict__ val,
+                                                  const double* __restrict__ dinv, double* __restrict__ part) {
+    __shared__ double sh[kT / 64];
+    double m = 0.0;
+    for (int64_t i = int64_t(blockIdx.x) * kT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kT) {
+        const int64_t sl = i / kSlice;
+        const int64_t base = off[sl] + (i - sl * kSlice);
+        double s = 0.0;
+        for (int k = 0; k < width[sl]; ++k) s += fabs(val[base + int64_t(kSlice) * k]);
+        m = fmax(m, fabs(dinv[i]) * s);
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sh[0];
+        for (int q = 1; q < kT / 64; ++q) t = fmax(t, sh[q]);
+        part[blockIdx.x] = t;
+    }
+}
+
+__global__ void __launch_bounds__(kT) k_max_partials(const double* __restrict__ part, int n, double* __restrict__ S,
+                                                    int slot) {
+    __shared__ double sh[kT / 64];
+    double m = 0.0;
+    for (int q = threadIdx.x; q < n; q += kT) m = fmax(m, part[q]);
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < kT / 64; ++q) m = fmax(m, sh[q]);
+        S[slot] = m;
+    }
 }
 
 // beta = rz_new / rz_old; p = z + beta p.  Block 0 stores rz_new in the next
@@ -381,9 +455,27 @@ hipError_t fem_shift(int64_t n, double* x, const double* S, int slot, hipStream_
     return hipGetLastError();
 }
 
+// the Chebyshev steps 1 .. deg - 1 after z_0 and d_0 are set in c.z and c.dk;
+// returns the buffer holding the final z (p = that z too when p is given)
+static double* cheb_steps(const FemCg& c, double* p, hipStream_t st) {
+    double* zin = c.z;
+    double* zout = c.z2;
+    for (int k = 1; k < c.deg; ++k) {
+        const bool last = k == c.deg - 1;
+        hipLaunchKernelGGL(k_cheb_step, dim3(kFemBlocks), dim3(kT), 0, st, c.n, c.off, c.width, c.col, c.val, c.dinv,
+                           c.r, zin, zout, c.dk, c.c1[k], c.c2[k], last ? p : nullptr, last ? c.part_rz : nullptr);
+        double* t = zin;
+        zin = zout;
+        zout = t;
+    }
+    return zin;
+}
+
 hipError_t fem_cg_start(const FemCg& c, const double* b, double* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_cg_start, dim3(kFemBlocks), dim3(kT), 0, st, c.n, b, c.dinv, x, c.r, c.z, c.p, c.part_rz,
-                       c.part_rr);
+    const bool cheb = c.deg > 1;
+    hipLaunchKernelGGL(k_cg_start, dim3(kFemBlocks), dim3(kT), 0, st, c.n, b, c.dinv, c.inv_theta, x, c.r, c.z, c.p,
+                       cheb ? c.dk : nullptr, c.part_rz, c.part_rr);
+    if (cheb) cheb_steps(c, c.p, st);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kT), 0, st, c.part_rz, int(kFemBlocks), c.S, kSlotRZ0, 1.0);
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kT), 0, st, c.part_rr, int(kFemBlocks), c.S, kSlotRR, 1.0);
     return hipGetLastError();
@@ -398,10 +490,18 @@ hipError_t fem_cg_step(const FemCg& c, double* x, int iter, hipStream_t st) {
     const unsigned nb = spmv_blocks(c.n);
     hipLaunchKernelGGL(k_spmv_dot, dim3(nb), dim3(kT), 0, st, c.n, c.off, c.width, c.col, c.val, c.p, c.q,
                        c.part_pq);
+    const bool cheb = c.deg > 1;
     hipLaunchKernelGGL(k_cg_update, dim3(kFemBlocks), dim3(kT), 0, st, c.n, int(nb), c.part_pq, c.S, rz_old, c.dinv,
-                       x, c.r, c.z, c.p, c.q, c.part_rz, c.part_rr);
+                       c.inv_theta, x, c.r, c.z, cheb ? c.dk : nullptr, c.p, c.q, c.part_rz, c.part_rr);
+    const double* z = cheb ? cheb_steps(c, nullptr, st) : c.z;
     hipLaunchKernelGGL(k_cg_direction, dim3(kFemBlocks), dim3(kT), 0, st, c.n, int(kFemBlocks), c.part_rz, c.part_rr,
-                       c.S, rz_old, rz_new, c.z, c.p);
+                       c.S, rz_old, rz_new, z, c.p);
+    return hipGetLastError();
+}
+
+hipError_t fem_gershgorin(const FemCg& c, double* part, double* S, int slot, hipStream_t st) {
+    hipLaunchKernelGGL(k_gershgorin, dim3(kFemBlocks), dim3(kT), 0, st, c.n, c.off, c.width, c.val, c.dinv, part);
+    hipLaunchKernelGGL(k_max_partials, dim3(1), dim3(kT), 0, st, part, int(kFemBlocks), S, slot);
     return hipGetLastError();
 }
 
