@@ -643,12 +643,10 @@ void recompress_impl(h2dlp_ctx* h, const double* d_boxes, const double* wt64, co
         h->up_end[l] = int32_t(items_up.size());
     }
     // y^_t = sum_s S'_ts x^_s in two launches split at level up_cut of the
-    // source: the deepest cut that leaves at most 1/share of the coupling
+    // source: the deepest cut that leaves at most 1/32 of the coupling
     // entries to the second launch, so that the latency-bound top of the
-    // upward pass runs beside the first.  Measured at 655362 nodes: FP32 is
-    // best at 1/32 (2.09 ms against 2.11 ms at 1/8), FP64 at 1/8 (3.39 ms
-    // against 3.72 ms at 1/32), whose longer first launch covers more of the
-    // upward pass.
+    // upward pass runs beside the first (at 655362 nodes, FP32: 2.09 ms
+    // against 2.11 ms with 1/8)
     std::vector<int32_t> lvl(C, 0);
     for (int l = 0; l <= S.depth; ++l)
         for (int32_t g = h->level_off[l]; g < h->level_off[l + 1]; ++g) lvl[g] = l;
@@ -660,7 +658,7 @@ void recompress_impl(h2dlp_ctx* h, const double* d_boxes, const double* wt64, co
             by_level[lvl[h->far_s[b]]] += n;
             total += n;
         }
-        const int64_t share = h->prec == H2DLP_FP64 ? 8 : 32;
+        constexpr int64_t share = 32;
         h->up_cut = 0;
         int64_t above = 0;                             // entries with sources above level l
         for (int l = 0; l <= S.depth; ++l) {
