@@ -147,13 +147,17 @@ __global__ void __launch_bounds__(256) k_gather_leaf(const GatherDesc* __restric
 // Rows to fold into one R: up to kFoldSeg segments [begin, begin + n) of the
 // rows of a column-major source (ld), folded in order.
 constexpr int kFoldSeg = 10;
-constexpr int kFoldChunk = 32;              // rows folded per Householder sweep
+constexpr int kFoldChunk = 64;              // rows folded per Householder sweep (one wavefront's lanes)
 struct FoldDesc {
     double* R;                              // k x k column-major, upper triangle: in (first init rows) and out
     const double* src;
     int32_t ld, init, nseg, pad;            // init: rows of R filled on entry (0: R starts at zero)
     int32_t seg_begin[kFoldSeg], seg_n[kFoldSeg];
 };
+
+// R(i, j), j >= i, in the packed upper triangle of a k x k R (row-major rows
+// of k - i entries)
+__device__ inline int packed(int i, int j, int k) { return i * k - (i * (i - 1)) / 2 + (j - i); }
 
 __device__ inline double wave_sum(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -170,16 +174,18 @@ __device__ inline double wave_sum(double v) {
 // also when the rows are rank-deficient (an unpivoted reflection from a zero
 // pivot would spread content into later rows).  A reflection touches only
 // R(j, :) and the chunk (R is triangular), so both stay in LDS; R(j, j) keeps
-// the sign the reflection gives.  kFoldTpc threads per column apply a
-// reflection (kFoldChunk / kFoldTpc chunk rows each); the workgroup is
-// kFoldThreads wide, since its LDS admits one per CU anyway.
+// the sign the reflection gives.  R is kept as its packed upper triangle, so
+// that LDS holds a chunk of 64 rows beside it.  kFoldTpc threads per column
+// apply a reflection (kFoldChunk / kFoldTpc chunk rows each); the workgroup
+// is kFoldThreads wide, since its LDS admits one per CU anyway.
 constexpr int kFoldThreads = 1024;
 constexpr int kFoldTpc = 8;
 static_assert(kFoldThreads / kFoldTpc >= 128, "one thread group per column of k <= 128");
+static_assert(kFoldChunk <= 64 && kFoldChunk % kFoldTpc == 0, "the first wavefront sums a chunk column");
 __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldDesc* __restrict__ desc, int k) {
     extern __shared__ double sm[];
-    double* Rs = sm;                        // k x k row-major
-    double* Cs = Rs + k * k;                // kFoldChunk x k row-major
+    double* Rs = sm;                        // packed upper triangle of R, k (k + 1) / 2
+    double* Cs = Rs + k * (k + 1) / 2;      // kFoldChunk x k row-major
     double* us = Cs + kFoldChunk * k;       // the reflection's chunk part
     __shared__ double s_tau;
     const FoldDesc& d = desc[blockIdx.x];       // read in place: its segment arrays are indexed at run time
@@ -187,7 +193,7 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldDesc* __restric
     int filled = min(max(d.init, 0), k);
     for (int e = tid; e < k * k; e += blockDim.x) {
         const int i = e / k, j = e % k;
-        Rs[e] = (i < filled && i <= j) ? d.R[i + int64_t(k) * j] : 0.0;
+        if (i <= j) Rs[packed(i, j, k)] = i < filled ? d.R[i + int64_t(k) * j] : 0.0;
     }
     int total = 0;
     for (int q = 0; q < d.nseg; ++q) total += d.seg_n[q];
@@ -213,7 +219,7 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldDesc* __restric
             if (tid < 64) {
                 const double cj = (tid < nrow && tid >= first) ? Cs[tid * k + j] : 0.0;
                 const double s2 = wave_sum(cj * cj);
-                const double a = mv >= 0 ? Cs[mv * k + j] : Rs[j * k + j];
+                const double a = mv >= 0 ? Cs[mv * k + j] : Rs[packed(j, j, k)];
                 double tau = 0.0, scale = 0.0, diag = a;
                 if (s2 > 0.0) {
                     const double nrm = sqrt(a * a + s2);
@@ -225,14 +231,14 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldDesc* __restric
                 if (tid < kFoldChunk) us[tid] = cj * scale;
                 if (tid == 0) {
                     s_tau = tau;
-                    Rs[j * k + j] = diag;
+                    Rs[packed(j, j, k)] = diag;
                 }
             }
             __syncthreads();
             const double tau = s_tau;
             const int l = j + 1 + tid / kFoldTpc, h = tid % kFoldTpc;
             if (l < k && (tau != 0.0 || mv >= 0)) {
-                const double r0 = mv >= 0 ? Cs[mv * k + l] : Rs[j * k + l];
+                const double r0 = mv >= 0 ? Cs[mv * k + l] : Rs[packed(j, l, k)];
                 double w = 0.0;
                 if (tau != 0.0) {
                     constexpr int H = kFoldChunk / kFoldTpc;
@@ -243,7 +249,7 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldDesc* __restric
 #pragma unroll
                     for (int i = 0; i < H; ++i) Cs[(h * H + i) * k + l] -= w * us[h * H + i];
                 }
-                if (h == 0) Rs[j * k + l] = r0 - w;
+                if (h == 0) Rs[packed(j, l, k)] = r0 - w;
             }
             __syncthreads();
         }
@@ -252,7 +258,7 @@ __global__ void __launch_bounds__(kFoldThreads) k_fold(const FoldDesc* __restric
     __syncthreads();
     for (int e = tid; e < k * k; e += blockDim.x) {
         const int i = e % k, j = e / k;
-        d.R[e] = i <= j ? Rs[i * k + j] : 0.0;
+        d.R[e] = i <= j ? Rs[packed(i, j, k)] : 0.0;
     }
 }
 
@@ -462,7 +468,7 @@ std::string recompress(const RecompressPlan& P, const double* d_boxes, const dou
     const int32_t C = P.n_clusters;
     const int64_t kk = int64_t(k) * k, rk = int64_t(rows) * k;
     if (k < 1 || k > 128 || rows < 2 * k) return "recompression needs k <= 128 and rows >= 2k";
-    const size_t lds_fold = sizeof(double) * (size_t(k) * k + size_t(kFoldChunk) * k + kFoldChunk);
+    const size_t lds_fold = sizeof(double) * (size_t(k) * (k + 1) / 2 + size_t(kFoldChunk) * k + kFoldChunk);
     const size_t lds_jac = sizeof(double) * (size_t(k + 1) * k + (k + 1)) + sizeof(int) * size_t(k + 1);
     {
         int dev = 0, lds = 0;
