@@ -86,6 +86,7 @@ class MeshSpec:
     coupling: str = "stored"          # "stored" | "generated" (coupling matrices recomputed in the apply)
     dense_far_max: int = 0            # admissible blocks with |t||s| <= this kept as exact entries
     recompress_eps: float = 0.0       # > 0: bases recompressed to adaptive ranks at this tolerance (stored coupling)
+    row_basis: str = "stored"         # "generated": leaf row bases evaluated in the apply (interpolation bases)
 
     @property
     def n_nodes(self) -> int:
@@ -168,13 +169,13 @@ class GpuBackend(Backend):
     def plan_bytes(self, spec):
         p = self.h2dlp.plan(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
                             coupling=spec.coupling, dense_far_max=spec.dense_far_max,
-                            recompress_eps=spec.recompress_eps)
+                            recompress_eps=spec.recompress_eps, row_basis=spec.row_basis)
         return p.stats.bytes_resident, p.stats.workspace_bytes
 
     def build(self, spec):
         return self.h2dlp.Operator(spec.xyz, spec.tri, spec.order, spec.leaf, spec.eta, spec.precision,
                                    device=self.dev_index, coupling=spec.coupling, dense_far_max=spec.dense_far_max,
-                                   recompress_eps=spec.recompress_eps)
+                                   recompress_eps=spec.recompress_eps, row_basis=spec.row_basis)
 
     def built_bytes(self, op):
         return op.stats.bytes_resident

@@ -64,13 +64,15 @@ def test_async_reload_then_apply_on_another_stream(mods):
         assert np.array_equal(d2.cpu().numpy(), before)
 
 
-@pytest.mark.parametrize("coupling,eps", [("stored", 0.0), ("generated", 0.0), ("stored", 1e-6)])
-def test_mix_equals_alone_under_budget(mods, coupling, eps):
+@pytest.mark.parametrize("coupling,eps,rb", [("stored", 0.0, "stored"), ("generated", 0.0, "stored"),
+                                             ("stored", 1e-6, "stored"), ("generated", 0.0, "generated")])
+def test_mix_equals_alone_under_budget(mods, coupling, eps, rb):
     # recompressed stored coupling is the mode the benchmark serves; a
     # recompressed operator is built when registered, for its exact size
     h2dlp, serving = mods
     ms = _meshes()
-    specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32", coupling=coupling, recompress_eps=eps)
+    specs = [serving.MeshSpec(k, x, t, order=4, leaf=32, precision="fp32", coupling=coupling, recompress_eps=eps,
+                              row_basis=rb)
              for k, (x, t) in ms.items()]
     backend = serving.GpuBackend(0)
     srv = serving.Server(backend, 0, n_slots=3, max_batch_rhs=24)
@@ -96,7 +98,7 @@ def test_mix_equals_alone_under_budget(mods, coupling, eps):
     assert sum(stats["offloads"].values()) > 0 and sum(stats["reloads"].values()) > 0
     assert stats["batches"] < 60
     alone_ops = {s.mesh_id: h2dlp.Operator(s.xyz, s.tri, s.order, s.leaf, s.eta, s.precision, coupling=coupling,
-                                           recompress_eps=eps)
+                                           recompress_eps=eps, row_basis=rb)
                  for s in specs}
     for r in reqs:
         assert np.array_equal(r.result, _apply(alone_ops[r.mesh_id], r.u1)), r.rid
