@@ -195,7 +195,14 @@ def _ptr(t) -> int:
 
 
 class Operator:
-    """A built H2 boundary operator resident on one GPU (owns its device memory)."""
+    """A built H2 boundary operator resident on one GPU (owns its device memory).
+
+    The options are those of h2dlp_options in include/h2dlp.h: precision
+    ("fp64", "fp32", "bf16x3", "bf16x6"), coupling ("stored" or "generated"),
+    dense_far_max (admissible blocks kept exact), recompress_eps (algebraic
+    recompression to adaptive ranks) and row_basis ("stored" or "generated":
+    leaf row bases evaluated in the apply).  plan_only builds the host
+    structure and byte counts without a GPU."""
 
     def __init__(self, xyz, tri, order: int = 4, leaf: int = 32, eta: float = 2.0,
                  precision="fp64", alpha: float = 0.1, device: int = -1, stream=None, plan_only: bool = False,
