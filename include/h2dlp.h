@@ -279,7 +279,7 @@ typedef struct {
 
 /* Build: the surface (faces of one tetrahedron only, oriented outward), the
  * boundary operator on it with `opt` (order, leaf, eta, precision, coupling,
- * dense_far_max, recompress_eps; device and stream as for h2dlp_build_ex),
+ * dense_far_max, recompress_eps, row_basis; device and stream as for h2dlp_build_ex),
  * the P1 stiffness matrix and the element geometry.  The volume is copied.
  * EINVAL for a bad volume (index out of range, degenerate tetrahedron, no
  * closed surface), else the errors of h2dlp_build_ex. */
@@ -295,8 +295,10 @@ int h2dlp_fem_boundary_nodes(h2dlp_fem f, int64_t* nodes);
 /* One field evaluation on `stream` (a hipStream_t, NULL = null stream).
  * m: n_tets x 3 FP64 device array (M per tetrahedron); h: n_tets x 3 FP64
  * device array, receives H; u1, u2: n_nodes FP64 device arrays for the two
- * potentials, or NULL.  Each solve stops at |r| <= tol |r0| or after max_iter
- * iterations; *res (may be NULL) receives the iterations, residuals and the
+ * potentials, or NULL.  Both solves are conjugate gradients in FP64, each
+ * iteration preconditioned by six Chebyshev steps on D^-1 A (D the diagonal,
+ * spectrum bounded by Gershgorin at build); each stops at |r| <= tol |r0| or
+ * after max_iter iterations; *res (may be NULL) receives the iterations, residuals and the
  * energy.  Returns when the evaluation is done.  EINVAL for a NULL handle,
  * m or h, a pointer that is not device memory of the handle's GPU, tol <= 0
  * or max_iter < 1; EDEVICE when a HIP call fails. */
